@@ -1,0 +1,268 @@
+#!/usr/bin/env python3
+"""Benchmark of the FP64 Jacobi3D hot path on one MI355X.
+
+Default workload (one JSON line): a 512^3 FP64 grid over-decomposed into
+8x8x8 blocks of 64^3, zero Dirichlet boundary, seeded U[0,1) interior.  One
+step is a whole solve: reset the interior from a copy resident in HBM, then
+1000 sweeps (each packs, exchanges and unpacks all halos and updates every
+block, fused into one kernel and replayed from a HIP graph) with the residual
+of the last sweep.  value = interior cells x sweeps / step time (GLUP/s).
+
+Other workloads (--workload): modes, sweep (1024^3 decompositions), batch,
+serve; each prints its own JSON lines.  Multi-GPU runs are not part of this
+build: --gpus above 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "FP64 Jacobi3D GLUP/s + % HBM peak; served solves/s, p50/p99 latency"
+HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E, published
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector, published
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def sweep_bytes(problem) -> int:
+    """Algorithmic bytes of one fused sweep over all blocks of a problem.
+
+    Per block: read and write every interior cell once (16 B/cell), read the
+    six halo faces (8 B/cell, global-boundary faces included), write each
+    face that has a neighbour into that neighbour's halo storage (8 B/cell).
+    """
+    from paper_2202_11819_amd import j3d
+    nb, ext = j3d.j3d_block_extents(problem)
+    total = 0
+    for bz, ez in enumerate(ext[2]):
+        for by, ey in enumerate(ext[1]):
+            for bx, ex in enumerate(ext[0]):
+                faces = [ey * ez, ey * ez, ex * ez, ex * ez, ex * ey, ex * ey]
+                has = [bx > 0, bx + 1 < nb[0], by > 0, by + 1 < nb[1], bz > 0, bz + 1 < nb[2]]
+                total += 16 * ex * ey * ez + 8 * sum(faces) + 8 * sum(f for f, h in zip(faces, has) if h)
+    return total
+
+
+def copy_bandwidth(nbytes=2 << 30, reps=10):
+    """Measured streaming copy (read + write bytes per second), GB/s."""
+    import torch
+    from paper_2202_11819_amd import j3d
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    st = torch.cuda.current_stream().cuda_stream
+    j3d.j3d_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, st)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        j3d.j3d_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, st)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(n, target_seconds=15.0):
+    """The oracle as it stands, on this host's cores, over a bounded sample."""
+    from oracle import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    threads = max(1, min(threads, 64))
+    cells = n[0] * n[1] * n[2]
+    t0 = time.perf_counter()
+    oracle.jacobi(n, 1, seed=1, nthreads=threads)
+    t1 = time.perf_counter() - t0
+    sweeps = max(1, min(1000, int(target_seconds / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.jacobi(n, sweeps, seed=1, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": round(cells * sweeps / dt / 1e9, 4), "unit": "GLUP/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n[0]}x{n[1]}x{n[2]} seeded grid, {sweeps} sweeps in {dt:.1f} s "
+                      f"(includes the oracle's set-up and copy-out)"}
+
+
+def bench_overdecomposed(args):
+    import torch
+    from paper_2202_11819_amd import api, j3d
+    from paper_2202_11819_amd import workloads as W
+
+    spec = W.overdecomposed(nb=args.blocks, edge=args.edge, iters=args.sweeps)
+    n, sweeps = spec.n, spec.iters
+    cells = n[0] * n[1] * n[2]
+    log(f"[bench] workload {n} as {spec.nblk} blocks, {sweeps} sweeps/step, mode {args.mode}")
+    s = api.Solver(n, nblk=spec.nblk, seed=spec.seed)
+    if args.tune:
+        v, zc, bpc = (int(x) for x in args.tune.split(","))
+        s.set_tune(v, zc, bpc)
+    u0 = s.get_interior_device()          # the seeded interior, kept resident in HBM
+    stream = torch.cuda.current_stream()
+    per_launch = sweep_bytes(s.problem)
+
+    def step(timing=None):
+        s.set_interior(u0)
+        if timing is not None:
+            timing[0].record(stream)
+        s.run(sweeps - 1, mode=args.mode)
+        if timing is not None:
+            timing[1].record(stream)
+        return s.run(1, mode="fused", residual=True)
+
+    for w in range(args.warmup):
+        step()
+        log(f"[bench] warmup {w + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    res = None
+    for k in range(args.steps):
+        res = step(evs[k])
+        log(f"[bench] step {k + 1}/{args.steps} done")
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = t_start.elapsed_time(t_end)
+    ms_step = ms_total / args.steps
+    kernel_ms = sum(a.elapsed_time(b) for a, b in evs) / (args.steps * (sweeps - 1))
+    glups = cells * sweeps / (ms_step * 1e-3) / 1e9
+    achieved = per_launch / (kernel_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(glups, 3), "unit": "GLUP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{n[0]}^3 FP64 grid as {spec.nblk[0]}x{spec.nblk[1]}x{spec.nblk[2]} blocks of "
+                               f"{n[0] // spec.nblk[0]}^3, zero Dirichlet boundary, seeded U[0,1) interior, "
+                               f"{sweeps} sweeps per step (pack+exchange+unpack+update fused, {args.mode})",
+                   "grid": list(n), "blocks": list(spec.nblk), "sweeps": sweeps, "mode": args.mode},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "kernel": "sweep_kernel", "bytes_per_launch": per_launch,
+                     "avg_launch_ms": round(kernel_ms, 4)},
+        "residual": res,
+        "wall_s": round(wall, 3),
+    }
+    s.close()
+    del u0
+    torch.cuda.empty_cache()
+    if not args.no_copy:
+        out["copy_GBps"] = round(copy_bandwidth(), 1)
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def bench_modes(args):
+    """The same grid in every mode (unfused per block, unfused per phase, fused, graph)."""
+    import torch
+    from paper_2202_11819_amd import api
+    from paper_2202_11819_amd import workloads as W
+
+    spec = W.overdecomposed(nb=args.blocks, edge=args.edge, iters=args.sweeps)
+    n = spec.n
+    cells = n[0] * n[1] * n[2]
+    s = api.Solver(n, nblk=spec.nblk, seed=spec.seed)
+    ref = None
+    for mode, iters in [("unfused_block", 10), ("unfused_phase", 100), ("fused", args.sweeps),
+                        ("graph", args.sweeps)]:
+        s2 = api.Solver(n, nblk=spec.nblk, seed=spec.seed)
+        s2.run(2, mode=mode)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s2.run(iters, mode=mode)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        out = {"metric": "FP64 Jacobi3D GLUP/s by execution mode", "value": round(cells * iters / ms / 1e6, 3),
+               "unit": "GLUP/s", "mode": mode, "sweeps": iters, "ms_per_sweep": round(ms / iters, 4),
+               "config": {"workload": f"{n[0]}^3 as {spec.nblk} blocks"}}
+        print(json.dumps(out), flush=True)
+        s2.close()
+        torch.cuda.empty_cache()
+    s.close()
+
+
+def bench_sweep(args):
+    """1024^3 at several decompositions: GLUP/s and effective GB/s vs block count."""
+    import torch
+    from paper_2202_11819_amd import api
+    from paper_2202_11819_amd import workloads as W
+
+    for label, spec in W.block_sweep(iters=args.sweep_iters):
+        n = spec.n
+        cells = n[0] * n[1] * n[2]
+        s = api.Solver(n, nblk=spec.nblk, split=spec.split, seed=spec.seed)
+        s.run(10, mode="graph")
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.run(spec.iters, mode="graph")
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        per = sweep_bytes(s.problem)
+        gbps = per * spec.iters / (ms * 1e-3) / 1e9
+        nblocks = spec.nblk[0] * spec.nblk[1] * spec.nblk[2]
+        print(json.dumps({"metric": "FP64 Jacobi3D GLUP/s vs decomposition", "workload": label,
+                          "blocks": nblocks, "value": round(cells * spec.iters / ms / 1e6, 3), "unit": "GLUP/s",
+                          "GBps": round(gbps, 1), "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4),
+                          "B_per_LUP": round(per / cells, 3), "sweeps": spec.iters,
+                          "ms_per_sweep": round(ms / spec.iters, 4)}), flush=True)
+        s.close()
+        torch.cuda.empty_cache()
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="overdecomposed",
+                    choices=["overdecomposed", "modes", "sweep", "batch", "serve"])
+    ap.add_argument("--mode", default="graph", choices=["graph", "fused", "unfused_phase", "unfused_block"])
+    ap.add_argument("--edge", type=int, default=512)
+    ap.add_argument("--blocks", type=int, default=8)
+    ap.add_argument("--sweeps", type=int, default=1000)
+    ap.add_argument("--sweep-iters", type=int, default=500)
+    ap.add_argument("--tune", default="", help="variant,zchunk,blocks_per_cu")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(every block of the decomposition sits on one MI355X).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    if args.workload == "overdecomposed":
+        bench_overdecomposed(args)
+    elif args.workload == "modes":
+        bench_modes(args)
+    elif args.workload == "sweep":
+        bench_sweep(args)
+    elif args.workload == "batch":
+        from paper_2202_11819_amd import serve
+        serve.bench_batch(args)
+    elif args.workload == "serve":
+        from paper_2202_11819_amd import serve
+        serve.bench_serve(args)
+
+
+if __name__ == "__main__":
+    main()

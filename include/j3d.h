@@ -1,0 +1,276 @@
+/*
+ * j3d.h -- C ABI of libj3d, an MI355X (gfx950) implementation of the FP64
+ * Jacobi3D hot path of Choi, Richards and Kale, "Improving Scalability with
+ * GPU-Aware Asynchronous Tasks" (arXiv 2202.11819).
+ *
+ * The method (Sec. II-A, Fig. 1, Fig. 3): a 3-D grid is over-decomposed into
+ * blocks; every iteration each block packs its six halo faces, hands them to
+ * its neighbours, unpacks the faces it receives, and applies the Jacobi
+ * update to its whole block, reading the previous iterate from one buffer and
+ * writing the next into the other (Sec. III-C).  Here every block sits on one
+ * GPU: halos move block to block in device memory.  Fused execution follows
+ * kernel-fusion strategy C (unpack, update and pack as one kernel,
+ * Sec. III-D-1) and graph execution follows Sec. III-D-2.
+ *
+ * Numerics (readings of what the paper leaves open):
+ *   u'(c) = (((((( u(c) + u(x-) ) + u(x+) ) + u(y-) ) + u(y+) ) + u(z-) ) + u(z+)) * fl(1/7)
+ * in IEEE binary64, round to nearest even, no contraction, denormals kept.
+ * Boundary: a fixed 1-cell Dirichlet layer (one constant per face, or a
+ * per-cell array per face).  Seeded interior: uniform [0,1) from SplitMix64,
+ * independent of the decomposition.  Residual: max over the interior of
+ * |u_new - u_old| for the last sweep, 0 when no sweep ran.  Every mode and
+ * every decomposition yields the same bits.
+ *
+ * Conventions for every call:
+ *   - Returns j3d_status; 0 is success, negative is an error.  No exception or
+ *     abort crosses the ABI.  j3d_last_error() gives this thread's message for
+ *     the last non-OK status.
+ *   - All validation happens before any device work: a call that fails with
+ *     J3D_EINVAL / J3D_ENOMEM / J3D_EBUDGET / J3D_EBUSY / J3D_ESTATE leaves
+ *     every object unchanged.  J3D_EDEVICE reports a HIP runtime error; the
+ *     object should then be destroyed.
+ *   - The caller owns the device arena (memory the library lays its data out
+ *     in; it never allocates device memory of its own except the pool's
+ *     copy-stream events), the HIP stream (void* holding a hipStream_t; NULL is
+ *     the default stream) and all host buffers.  Handles are opaque and not
+ *     thread-safe: use one host thread per handle.
+ *   - Device arrays and arenas must be 256-byte aligned.
+ *   - Work is enqueued asynchronously on the handle's stream unless a call
+ *     says it synchronises.
+ *   - Dense grid arrays are interior cells only, x fastest, then y, then z
+ *     (nx*ny*nz doubles), independent of the decomposition.
+ */
+#ifndef J3D_H
+#define J3D_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    J3D_OK = 0,
+    J3D_EINVAL = -1,  /* bad argument */
+    J3D_ENOMEM = -2,  /* arena too small */
+    J3D_EBUDGET = -3, /* pool: not enough free budget for this request */
+    J3D_EBUSY = -4,   /* pool: no free slot */
+    J3D_EDEVICE = -5, /* HIP runtime error, or no usable gfx950 device */
+    J3D_ESTATE = -6   /* call not valid in the object's current state */
+} j3d_status;
+
+/* How j3d_run drives the iterations (Sec. III-D).
+ *  UNFUSED_BLOCK: per block and iteration, six pack kernels, six device copies,
+ *                 six unpack kernels and one update kernel (no fusion: the
+ *                 paper's baseline with one launch stream of GPU operations
+ *                 per over-decomposed block).
+ *  UNFUSED_PHASE: per iteration one fused pack kernel (strategy A shape: one
+ *                 thread per cell of the largest face, each thread visiting
+ *                 the six faces), one exchange copy kernel, one fused unpack
+ *                 kernel (strategy B) and one update kernel, all blocks at once.
+ *  FUSED:         per iteration one kernel for all blocks that reads its halos
+ *                 where the neighbours left them, updates, and writes its new
+ *                 face values straight into the neighbours' halo storage of
+ *                 the next iterate (strategy C, generalised to all blocks).
+ *  GRAPH:         FUSED iterations captured once into a HIP graph holding an
+ *                 even number of sweeps (both buffer parities), replayed.    */
+typedef enum {
+    J3D_UNFUSED_BLOCK = 0,
+    J3D_UNFUSED_PHASE = 1,
+    J3D_FUSED = 2,
+    J3D_GRAPH = 3
+} j3d_mode;
+
+/* One Jacobi3D problem.
+ *  n[a]       interior cells along x, y, z; each >= 1.
+ *  nblk[a]    blocks along each axis.  All three 0: the surface-minimising
+ *             split of auto_parts blocks (Sec. IV-A; see j3d_auto_split),
+ *             auto_parts 0 meaning one block.
+ *  split[a]   optional explicit block extents along axis a (nblk[a] entries,
+ *             each >= 1, summing to n[a]); NULL: even split, which requires
+ *             n[a] % nblk[a] == 0.  Only read during the call it is passed to.
+ *  bc[f]      Dirichlet value of global face f: 0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+.
+ *  seed, pid  the seeded interior: problem pid's SplitMix64 stream of seed
+ *             (the stream's start state is the generator's (pid+1)-th output
+ *             from state seed; cell g = i + nx*(j + ny*k) takes output g+1 of
+ *             that stream, mapped to [0,1) as (h >> 11) * 2^-53).            */
+typedef struct {
+    int64_t n[3];
+    int32_t nblk[3];
+    int32_t auto_parts;
+    const int64_t *split[3];
+    double bc[6];
+    uint64_t seed;
+    uint64_t pid;
+} j3d_problem;
+
+/* Kernel shape for the sweep.  variant: index into the compiled tile shapes
+ * (j3d_variant_info); -1 picks by block size.  zchunk: z-planes per tile
+ * (>= 1; 0 = whole block depth).  blocks_per_cu: 0 launches one workgroup
+ * per tile; > 0 launches a persistent grid of blocks_per_cu workgroups per
+ * compute unit that take tiles from per-XCD queues.  Tile shape and
+ * scheduling never change the result bits.                                   */
+typedef struct {
+    int32_t variant;
+    int32_t zchunk;
+    int32_t blocks_per_cu;
+} j3d_tune;
+
+typedef struct j3d_solver j3d_solver;
+typedef struct j3d_batch j3d_batch;
+typedef struct j3d_pool j3d_pool;
+
+/* ---- host-only queries (no device needed) ------------------------------ */
+
+/* Thread-local text of the last non-OK status on this thread ("" if none). */
+const char *j3d_last_error(void);
+
+/* Library version string. */
+const char *j3d_version(void);
+
+/* Surface-minimising split of an n[0] x n[1] x n[2] grid into exactly `parts`
+ * blocks (Sec. IV-A: the grid is decomposed so that the total surface area,
+ * which sets the communication volume, is smallest).  Only factorisations
+ * with nblk[a] <= n[a] are considered; ties go to the one with the most
+ * blocks along z, then along y.  The chosen counts need not divide n[a]:
+ * uneven extents follow the j3d_block_extents rule.  EINVAL if parts < 1 or
+ * no factorisation fits.                                                     */
+j3d_status j3d_auto_split(const int64_t n[3], int32_t parts, int32_t nblk_out[3]);
+
+/* Resolved decomposition of a problem: nblk_out[3] blocks per axis and, if
+ * extents_out is non-NULL, the extents along x, then y, then z
+ * (nblk[0]+nblk[1]+nblk[2] values, at most cap).  Auto splits whose counts
+ * do not divide n[a] give the first n[a] % nblk[a] blocks one extra cell.   */
+j3d_status j3d_block_extents(const j3d_problem *p, int32_t nblk_out[3],
+                             int64_t *extents_out, int64_t cap);
+
+/* Device bytes j3d_create needs for this problem (fields, halo storage,
+ * send/receive buffers of the unfused modes, descriptor tables, staging).   */
+j3d_status j3d_arena_bytes(const j3d_problem *p, uint64_t *bytes);
+
+/* Bytes of the two field copies only (interior plus halo storage). */
+j3d_status j3d_field_bytes(const j3d_problem *p, uint64_t *bytes);
+
+/* Compiled sweep tile shapes: variant i covers tile_x x tile_y cells of an
+ * x-y plane with `threads` threads.  Returns EINVAL past the last variant. */
+j3d_status j3d_variant_info(int32_t variant, int32_t *tile_x, int32_t *tile_y,
+                            int32_t *threads);
+
+/* ---- plain solver -------------------------------------------------------- */
+
+/* Lay out problem p in dev_arena (arena_bytes >= j3d_arena_bytes(p)) and
+ * enqueue the seeded initialisation on hip_stream.  ENOMEM if the arena is too
+ * small, EDEVICE if no gfx950 device is current.                             */
+j3d_status j3d_create(const j3d_problem *p, void *dev_arena, uint64_t arena_bytes,
+                      void *hip_stream, j3d_solver **out);
+
+/* Replace the current interior with src (dense nx*ny*nz).  src_on_device: 1 if
+ * src is device memory, 0 for host memory (then the call synchronises).     */
+j3d_status j3d_set_interior(j3d_solver *s, const double *src, int src_on_device);
+
+/* Per-cell Dirichlet values for global face f (0..5), overriding bc[f].
+ * Layouts: x-faces ny*nz (y fastest), y-faces nx*nz (x fastest), z-faces nx*ny
+ * (x fastest).  src_on_device as above.                                     */
+j3d_status j3d_set_face(j3d_solver *s, int32_t face, const double *src, int src_on_device);
+
+/* Choose the sweep kernel shape (see j3d_tune); NULL restores the default. */
+j3d_status j3d_set_tune(j3d_solver *s, const j3d_tune *t);
+
+/* Enqueue `iters` (>= 0) Jacobi iterations in the given mode.  If residual_out
+ * is non-NULL the last sweep's residual is written there and the call
+ * synchronises; otherwise it returns once the work is enqueued.              */
+j3d_status j3d_run(j3d_solver *s, int64_t iters, j3d_mode mode, double *residual_out);
+
+/* Iterations performed since creation or the last j3d_set_interior. */
+j3d_status j3d_iters_done(const j3d_solver *s, int64_t *iters);
+
+/* Copy the current interior to dst (dense nx*ny*nz).  Synchronises for host
+ * destinations; device destinations are written asynchronously.            */
+j3d_status j3d_get_interior(j3d_solver *s, double *dst, int dst_on_device);
+
+/* Release the solver's host objects (graphs, tables); the arena stays the
+ * caller's.  Synchronises the stream first.                                 */
+j3d_status j3d_destroy(j3d_solver *s);
+
+/* ---- batched form: many independent problems, one launch per step ------- */
+
+/* Device bytes for a batch of `count` problems. */
+j3d_status j3d_batch_arena_bytes(int32_t count, const j3d_problem *probs, uint64_t *bytes);
+
+/* Lay out `count` problems (each with its own decomposition, boundary and
+ * seed) and their iteration counts iters[i] >= 0, and enqueue their seeded
+ * initialisation.  tune may be NULL (default shape).                        */
+j3d_status j3d_batch_create(int32_t count, const j3d_problem *probs, const int64_t *iters,
+                            void *dev_arena, uint64_t arena_bytes, void *hip_stream,
+                            const j3d_tune *tune, j3d_batch **out);
+
+/* Run every problem to its iteration count: step s is one launch covering
+ * every tile of every problem with iters > s.  residuals_out (count doubles
+ * or NULL) receives each problem's last-sweep residual; with it the call
+ * synchronises.  A batch runs once; ESTATE afterwards.                       */
+j3d_status j3d_batch_run(j3d_batch *b, double *residuals_out);
+
+/* Copy problem i's interior to dst (dense).  Synchronises for host dst. */
+j3d_status j3d_batch_get_interior(j3d_batch *b, int32_t i, double *dst, int dst_on_device);
+
+j3d_status j3d_batch_destroy(j3d_batch *b);
+
+/* ---- served form: continuous batching under an HBM budget ---------------- */
+
+/* Device bytes one request of problem p occupies in a pool. */
+j3d_status j3d_pool_request_bytes(const j3d_problem *p, uint64_t *bytes);
+
+/* A pool over dev_arena: budget_bytes of it hold request grids, the rest (see
+ * j3d_pool_overhead_bytes) its tables.  At most max_slots requests are
+ * resident.  The pool creates one extra stream for result copies.           */
+j3d_status j3d_pool_overhead_bytes(int32_t max_slots, uint64_t *bytes);
+j3d_status j3d_pool_create(void *dev_arena, uint64_t arena_bytes, uint64_t budget_bytes,
+                           int32_t max_slots, void *hip_stream, j3d_pool **out);
+
+/* Admit a request: solve p for at most max_iters sweeps, evaluating the
+ * residual every check_every sweeps (0: only at the end) and at max_iters,
+ * stopping once it is <= tol (tol <= 0: never early).  host_result (nx*ny*nz
+ * doubles, best page-locked) receives the final interior when the request
+ * finishes.  EBUSY without a free slot, EBUDGET without enough free budget;
+ * nothing changes then.  The request joins the next round.                 */
+j3d_status j3d_pool_admit(j3d_pool *pl, const j3d_problem *p, int64_t max_iters, double tol,
+                          int32_t check_every, double *host_result, int32_t *slot);
+
+/* Enqueue one round of up to `sweeps` sweeps for every running request (each
+ * request stops at its own limit).  Asynchronous.  ESTATE if a round is still
+ * in flight (poll first).                                                   */
+j3d_status j3d_pool_step(j3d_pool *pl, int32_t sweeps);
+
+/* Non-blocking progress: retires a completed round (updating every request's
+ * sweep count and residual, deciding which finished), starts the result
+ * copies of finished requests, and reports in done[] (at most cap) the slots
+ * whose results have fully arrived in host memory since the last poll.
+ * *round_busy is set to 1 while a round is still in flight.                 */
+j3d_status j3d_pool_poll(j3d_pool *pl, int32_t *done, int32_t cap, int32_t *n_done,
+                         int32_t *round_busy);
+
+/* Residual and sweep count of a finished request. */
+j3d_status j3d_pool_result(j3d_pool *pl, int32_t slot, double *residual, int64_t *iters_done);
+
+/* Free a finished (or still queued/running: cancel) request's slot and bytes. */
+j3d_status j3d_pool_release(j3d_pool *pl, int32_t slot);
+
+/* Occupancy: resident requests and bytes in use. */
+j3d_status j3d_pool_usage(const j3d_pool *pl, int32_t *slots_used, uint64_t *bytes_used);
+
+j3d_status j3d_pool_destroy(j3d_pool *pl);
+
+/* ---- measurement helpers ------------------------------------------------- */
+
+/* Enqueue a plain device copy of `bytes` (multiple of 16) from src to dst: the
+ * streaming-bandwidth reference kernel used to calibrate HBM counters.      */
+j3d_status j3d_device_copy(void *dst, const void *src, uint64_t bytes, void *hip_stream);
+
+/* Number of compute units of the current device (EDEVICE without a device). */
+j3d_status j3d_device_cus(int32_t *cus);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* J3D_H */

@@ -1,0 +1,164 @@
+"""Torch-owned device memory around the C ABI: Solver, Batch and Pool.
+
+These classes only allocate the arena (a uint8 CUDA/HIP tensor), pick the
+stream and marshal arrays; every computation runs in libj3d.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import j3d as C
+
+
+def _stream(stream):
+    return stream if stream is not None else torch.cuda.current_stream()
+
+
+class Solver:
+    """One Jacobi3D problem, over-decomposed into blocks on one GPU."""
+
+    def __init__(self, n, nblk=(1, 1, 1), split=None, bc=0.0, seed=1, pid=0, auto_parts=0,
+                 stream=None, device="cuda"):
+        self.problem = C.Problem(n, nblk, split, bc, seed, pid, auto_parts)
+        self.n = tuple(int(v) for v in n)
+        self.arena_bytes = C.j3d_arena_bytes(self.problem)
+        self.arena = torch.empty(self.arena_bytes, dtype=torch.uint8, device=device)
+        self.stream = _stream(stream)
+        self.h = C.j3d_create(self.problem, self.arena.data_ptr(), self.arena_bytes, self.stream.cuda_stream)
+
+    @property
+    def shape(self):
+        return (self.n[2], self.n[1], self.n[0])
+
+    def run(self, iters, mode="graph", residual=False):
+        return C.j3d_run(self.h, iters, mode, residual)
+
+    def set_tune(self, variant=-1, zchunk=0, blocks_per_cu=0):
+        C.j3d_set_tune(self.h, variant, zchunk, blocks_per_cu)
+
+    def set_interior(self, u):
+        if isinstance(u, torch.Tensor) and u.is_cuda:
+            u = u.contiguous().to(torch.float64)
+            C.j3d_set_interior(self.h, u.data_ptr(), True)
+            self.stream.synchronize()
+        else:
+            a = np.ascontiguousarray(np.asarray(u, dtype=np.float64))
+            assert a.size == self.n[0] * self.n[1] * self.n[2]
+            C.j3d_set_interior(self.h, a.ctypes.data, False)
+
+    def set_face(self, face, values):
+        a = np.ascontiguousarray(np.asarray(values, dtype=np.float64))
+        C.j3d_set_face(self.h, face, a.ctypes.data, False)
+
+    def get_interior(self) -> np.ndarray:
+        out = np.empty(self.shape, dtype=np.float64)
+        C.j3d_get_interior(self.h, out.ctypes.data, False)
+        return out
+
+    def get_interior_device(self) -> torch.Tensor:
+        out = torch.empty(self.shape, dtype=torch.float64, device=self.arena.device)
+        C.j3d_get_interior(self.h, out.data_ptr(), True)
+        self.stream.synchronize()
+        return out
+
+    def iters_done(self):
+        return C.j3d_iters_done(self.h)
+
+    def close(self):
+        if self.h is not None:
+            C.j3d_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Batch:
+    """Many independent problems advanced by one launch per sweep."""
+
+    def __init__(self, problems, iters, tune=None, stream=None, device="cuda"):
+        self.problems = list(problems)
+        self.iters = [int(v) for v in iters]
+        self.arena_bytes = C.j3d_batch_arena_bytes(self.problems)
+        self.arena = torch.empty(self.arena_bytes, dtype=torch.uint8, device=device)
+        self.stream = _stream(stream)
+        self.h = C.j3d_batch_create(self.problems, self.iters, self.arena.data_ptr(), self.arena_bytes,
+                                    self.stream.cuda_stream, tune)
+
+    def run(self, residuals=True):
+        return C.j3d_batch_run(self.h, len(self.problems), residuals)
+
+    def get_interior(self, i) -> np.ndarray:
+        n = self.problems[i].n
+        out = np.empty((n[2], n[1], n[0]), dtype=np.float64)
+        C.j3d_batch_get_interior(self.h, i, out.ctypes.data, False)
+        return out
+
+    def close(self):
+        if self.h is not None:
+            C.j3d_batch_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Pool:
+    """Continuous batching of solve requests under an HBM budget."""
+
+    def __init__(self, budget_bytes, max_slots=256, stream=None, device="cuda"):
+        self.overhead = C.j3d_pool_overhead_bytes(max_slots)
+        self.arena_bytes = self.overhead + int(budget_bytes)
+        self.arena = torch.empty(self.arena_bytes, dtype=torch.uint8, device=device)
+        self.stream = _stream(stream)
+        self.max_slots = max_slots
+        self.h = C.j3d_pool_create(self.arena.data_ptr(), self.arena_bytes, int(budget_bytes), max_slots,
+                                   self.stream.cuda_stream)
+        self.results = {}
+
+    def try_admit(self, problem, max_iters, tol=0.0, check_every=50):
+        """Returns the slot or None when no slot / budget is free."""
+        n = problem.n
+        host = torch.empty(n[0] * n[1] * n[2], dtype=torch.float64, pin_memory=True)
+        st, slot = C.j3d_pool_try_admit(self.h, problem, max_iters, tol, check_every, host.data_ptr())
+        if st != C.J3D_OK:
+            return None
+        self.results[slot] = (host, (n[2], n[1], n[0]))
+        return slot
+
+    def step(self, sweeps=50):
+        C.j3d_pool_step(self.h, sweeps)
+
+    def poll(self):
+        return C.j3d_pool_poll(self.h, self.max_slots)
+
+    def result(self, slot):
+        """(interior as numpy (nz,ny,nx), residual, sweeps done) of a finished slot."""
+        r, it = C.j3d_pool_result(self.h, slot)
+        host, shape = self.results[slot]
+        return host.numpy().reshape(shape), r, it
+
+    def release(self, slot):
+        C.j3d_pool_release(self.h, slot)
+        self.results.pop(slot, None)
+
+    def usage(self):
+        return C.j3d_pool_usage(self.h)
+
+    def close(self):
+        if self.h is not None:
+            C.j3d_pool_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

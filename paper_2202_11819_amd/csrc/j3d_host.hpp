@@ -1,0 +1,93 @@
+// j3d_host.hpp -- host-side planning shared by the solver, batch and pool.
+//
+// Planning is pure host code (no HIP calls): it resolves each problem's
+// decomposition (Sec. IV-A), builds the block table with its neighbour links
+// (the 3-D chare array of Fig. 3 and its idx[dir] proxies, as plain indices),
+// assigns every array its place in the caller's arena, and cuts blocks into
+// sweep tiles.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "j3d_internal.hpp"
+
+namespace j3d {
+
+// ---- errors --------------------------------------------------------------------
+
+j3d_status set_error(j3d_status st, const char *fmt, ...);
+void clear_error();
+
+// ---- host SplitMix64 (start state of a problem's stream) -----------------------
+
+// The (pid+1)-th output of SplitMix64 started in state `seed`.
+uint64_t stream_start(uint64_t seed, uint64_t pid);
+
+// ---- decomposition -------------------------------------------------------------
+
+struct Decomp {
+    int64_t n[3];
+    int32_t nb[3];
+    std::vector<int64_t> ext[3];  // block extents per axis
+    std::vector<int64_t> org[3];  // block origins per axis
+};
+
+j3d_status resolve_decomp(const j3d_problem *p, Decomp *d);
+j3d_status auto_split(const int64_t n[3], int32_t parts, int32_t nb[3]);
+
+// ---- arena plan ----------------------------------------------------------------
+
+struct ProbPlan {
+    Decomp d;
+    double bc[6];
+    uint64_t s0;
+    int32_t block_begin = 0, nblocks = 0;
+    uint64_t maps_off = 0;        // bytes: int32 pairs, x then y then z
+    uint64_t field_cells = 0;     // doubles of one parity's fields (all blocks)
+    uint64_t f_off[2] = {0, 0};   // bytes: start of the problem's fields per parity
+    int64_t iters = 0;            // batch: sweeps to run
+};
+
+struct Plan {
+    std::vector<BlockDesc> blocks;
+    std::vector<ProbPlan> probs;
+    bool with_sr = true;          // send/receive buffers of the unfused modes
+    uint64_t off_blocks = 0, off_probs = 0, off_tiles = 0, off_res = 0, off_queue = 0;
+    uint64_t off_bounce = 0, bounce_doubles = 0;
+    uint64_t tiles_cap = 0;
+    uint64_t total = 0;           // arena bytes
+    int32_t max_face = 0;         // largest face (cells) over all blocks
+    int32_t max_cells = 0;        // largest ghosted field (cells) over all blocks
+};
+
+// Plan `count` problems; the bounce area holds at least min_bounce doubles
+// (and at least the largest plane and face of every problem).
+j3d_status make_plan(int32_t count, const j3d_problem *probs, bool with_sr, Plan *plan);
+
+// Tiles of blocks [b0, b1) for a variant and z-chunk (0 = whole block), block
+// by block, z then y then x slowest to fastest.
+void make_tiles(const Plan &plan, int32_t b0, int32_t b1, int variant, int zchunk,
+                std::vector<Tile> *tiles, std::vector<int32_t> *block_first);
+
+// Default sweep shape for the blocks of a plan.
+void default_tune(const Plan &plan, int cus, j3d_tune *t);
+
+// Number of tiles that variant/zchunk give over the blocks of a plan.
+uint64_t count_tiles(const Plan &plan, int variant, int zchunk);
+
+// Validates a tune against a plan; fills the effective z-chunk.
+j3d_status check_tune(const Plan &plan, const j3d_tune *t, int *zchunk_eff);
+
+// Ghosted cells of one block's field (one parity).
+inline int64_t block_field_cells(int64_t ex, int64_t ey, int64_t ez)
+{
+    return ex * (ey + 2) * (ez + 2);
+}
+
+inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+constexpr int kMinZchunk = 4;
+
+}  // namespace j3d

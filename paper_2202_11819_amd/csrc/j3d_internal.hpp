@@ -1,0 +1,132 @@
+// j3d_internal.hpp -- descriptors shared by the host engine and the HIP kernels.
+//
+// Memory layout of one block b (interior extents ex, ey, ez) for each of the
+// two iterates (parity 0 and 1; Sec. III-C keeps two copies of the block and
+// swaps their roles every iteration):
+//
+//   field  F[p][b]: (ez+2) planes x (ey+2) rows x ex doubles, x fastest.
+//          Plane 0 and plane ez+1 hold the z- / z+ halos, row 0 and row ey+1
+//          of every plane hold the y- / y+ halos; interior cell (x, y, z) sits
+//          at ((z+1)*(ey+2) + (y+1))*ex + x.  Rows are dense (no x ghosts), so
+//          a row of the interior and a y- or z-halo row are the same contiguous
+//          ex doubles; edge rows of the halo planes are never read.
+//   x-halo X[p][b]: two arrays of ey*ez doubles (x- then x+), y fastest.  The
+//          x-halos live apart from the rows so that a neighbour writes them as
+//          contiguous runs instead of one double per row.
+//
+// A global-boundary face holds its Dirichlet values in the same halo storage,
+// written once for both parities; interior faces are written by neighbours.
+// The unfused modes also use per-block contiguous send and receive buffers
+// S[b], R[b], each the six faces in the order x-, x+, y-, y+, z-, z+ with
+// sizes ey*ez, ey*ez, ex*ez, ex*ez, ex*ey, ex*ey (Fig. 1's send_halo/recv_halo).
+#pragma once
+
+#include <cstdint>
+
+#include "../../include/j3d.h"
+
+namespace j3d {
+
+// Face numbering: 0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+.  opp(f) = f ^ 1.
+
+struct BlockDesc {          // 128 bytes, read by kernels through scalar loads
+    int64_t off[2];         // F[p][b] offset, in doubles from the arena base
+    int64_t xoff[2];        // X[p][b] offset (x- array, then x+ array)
+    int64_t sr_off;         // S[b] offset; R[b] follows at sr_off + face_total
+    int64_t face_total;     // 2*ey*ez + 2*ex*ez + 2*ex*ey
+    int32_t ext[3];         // ex, ey, ez
+    int32_t prob;           // index of the owning problem in the problem table
+    int32_t nbr[6];         // neighbour block per face (table index) or -1
+    int32_t org[3];         // global coordinates of the block's first cell
+    int32_t pad[7];
+};
+static_assert(sizeof(BlockDesc) == 128, "BlockDesc layout");
+
+// Problem state seen by the multi-problem sweep (batched and served forms).
+struct ProbDesc {           // 64 bytes
+    int64_t base;           // sweeps already done when step 0 of this launch sequence runs
+    int64_t limit;          // sweep count at which the problem stops
+    int32_t check_every;    // residual every k-th sweep (0: only at `limit`)
+    int32_t res_slot;       // index of the problem's residual word
+    int32_t flags;          // PF_RES_LAST: evaluate the residual at `limit`
+    int32_t pad0;
+    int64_t pad[4];
+};
+static_assert(sizeof(ProbDesc) == 64, "ProbDesc layout");
+
+enum : int32_t { PF_RES_LAST = 1 };
+
+// One sweep tile: block index and tile coordinates along x, y, z.
+struct Tile {
+    int32_t block, tx, ty, tz;
+};
+
+enum : int32_t {
+    SW_FUSED = 1,   // write new face values into the neighbours' next halo storage
+    SW_RES = 2,     // plain mode: residual of this sweep into res[0] (via the block's problem)
+    SW_MULTI = 4,   // per-problem activity, parity and residual policy from ProbDesc
+    SW_PERSIST = 8  // persistent grid with per-XCD tile queues
+};
+
+struct SweepArgs {
+    double *base;                 // arena base
+    const BlockDesc *blocks;
+    const ProbDesc *probs;
+    const Tile *tiles;
+    unsigned long long *res;      // residual words (bit patterns of non-negative doubles)
+    unsigned int *queue;          // persistent mode: 2 x 8 tile counters
+    int64_t step;                 // multi mode: sweep index of this launch
+    int32_t tile_begin;
+    int32_t tile_count;
+    int32_t zchunk;
+    int32_t parity;               // plain mode: parity of the input iterate
+    int32_t flags;
+    int32_t queue_slot;           // persistent mode: which half of `queue` this launch uses
+};
+
+// ---- kernel variants ----------------------------------------------------------
+
+struct VariantInfo {
+    int tile_x, tile_y, threads;
+};
+int variant_count();
+VariantInfo variant_info(int v);
+
+// ---- launchers (defined in j3d_kernels.hip); all enqueue on `stream` ----------
+// Every launcher returns 0 or a hipError_t value.
+
+int launch_sweep(int variant, const SweepArgs &a, int grid, void *stream);
+// Init: interior of parity `parity` from SplitMix64 state s0 (global dims n),
+// halo storage of both parities: Dirichlet value on global faces, NaN elsewhere.
+int launch_init(double *base, const BlockDesc *blocks, int32_t block_begin, int32_t nblocks,
+                int32_t max_cells, int32_t max_xface, int parity, const int64_t n[3], uint64_t s0,
+                const double bc[6], int write_interior, void *stream);
+// Pack (faces in `face_mask`) of parity `parity` into send buffers.
+int launch_pack(double *base, const BlockDesc *blocks, int32_t block_begin, int32_t nblocks,
+                int32_t max_face, int parity, int face_mask, void *stream);
+// Exchange S[b][f] -> R[nbr][opp f] for all blocks in the range.
+int launch_exchange(double *base, const BlockDesc *blocks, int32_t block_begin, int32_t nblocks,
+                    int32_t max_face, void *stream);
+// Unpack R[b][f] into the halo storage of parity `parity`.
+int launch_unpack(double *base, const BlockDesc *blocks, int32_t block_begin, int32_t nblocks,
+                  int32_t max_face, int parity, int face_mask, void *stream);
+// Dense global array chunk (planes z0..z1-1) <-> block interiors of parity p.
+// maps: for axis a, n[a] pairs (block coordinate, local coordinate).
+int launch_scatter(double *base, const BlockDesc *blocks, int32_t block_base, const int32_t nb[3],
+                   const int32_t *maps, const int64_t n[3], int64_t z0, int64_t z1,
+                   const double *src, int parity, void *stream);
+int launch_gather(const double *base, const BlockDesc *blocks, int32_t block_base,
+                  const int32_t nb[3], const int32_t *maps, const int64_t n[3], int64_t z0,
+                  int64_t z1, double *dst, int parity, void *stream);
+// Per-cell Dirichlet face f from a dense device array into both parities.
+int launch_set_face(double *base, const BlockDesc *blocks, int32_t block_base, const int32_t nb[3],
+                    const int32_t *maps, const int64_t n[3], int face, const double *src,
+                    void *stream);
+int launch_fill_u64(unsigned long long *p, int64_t count, unsigned long long value, void *stream);
+int launch_fill_u32(unsigned int *p, int64_t count, unsigned int value, void *stream);
+int launch_copy(void *dst, const void *src, uint64_t bytes, void *stream);
+// Dense interior of one single-block problem gathered into `dst` (device).
+int launch_gather_block(const double *base, const BlockDesc *blocks, int32_t block, int parity,
+                        double *dst, void *stream);
+
+}  // namespace j3d

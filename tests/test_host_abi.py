@@ -1,0 +1,176 @@
+"""Host-only checks of the C ABI: exports, decomposition, arena sizing, validation.
+
+No call here touches a GPU: every function used is pure host code, or fails
+validation before any device work.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2202_11819_amd import j3d
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "j3d.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return set(re.findall(r"^\s*(?:j3d_status|const char \*)\s*(j3d_\w+)\s*\(", text, flags=re.M))
+
+
+def test_library_exports_every_declared_symbol():
+    declared = _declared_functions()
+    assert len(declared) >= 30
+    for name in declared:
+        assert hasattr(j3d._lib, name), name
+    assert declared == set(j3d.EXPORTED)
+
+
+def test_version_and_no_error():
+    assert "gfx950" in j3d.j3d_version()
+
+
+# ---- decomposition (Sec. IV-A: surface-minimising split) -------------------------
+
+def _paper_rows():
+    rows = []
+    with open(os.path.join(GOLDEN, "paper_memory_sizes.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                edge, gpus, sx, sy, sz, nbytes = line.split()
+                rows.append((int(edge), int(gpus), (int(sx), int(sy), int(sz)), float(nbytes)))
+    return rows
+
+
+@pytest.mark.parametrize("row", _paper_rows())
+def test_paper_node_split_and_memory(row):
+    edge, gpus, split, paper_bytes = row
+    assert j3d.j3d_auto_split((edge,) * 3, gpus) == split
+    nb, ext = j3d.j3d_block_extents(j3d.Problem((edge,) * 3, None, auto_parts=gpus))
+    assert nb == split
+    blk = tuple(e[0] for e in ext)
+    assert all(len(set(e)) == 1 for e in ext)  # even split
+    # two copies of one GPU's block (interior cells); the paper says "roughly"
+    two_fields = 2 * 8 * blk[0] * blk[1] * blk[2]
+    assert 0.95 * paper_bytes <= two_fields <= 1.1 * paper_bytes
+    # the library's fields add halo storage only
+    fb = j3d.j3d_field_bytes(j3d.Problem(blk))
+    assert two_fields < fb < 1.1 * two_fields
+
+
+def test_auto_split_prefers_small_surface():
+    assert j3d.j3d_auto_split((64, 64, 64), 1) == (1, 1, 1)
+    assert j3d.j3d_auto_split((64, 64, 64), 8) == (2, 2, 2)
+    assert j3d.j3d_auto_split((512, 512, 512), 512) == (8, 8, 8)
+    assert j3d.j3d_auto_split((1000, 10, 10), 4) == (4, 1, 1)
+    with pytest.raises(j3d.J3DError) as e:
+        j3d.j3d_auto_split((2, 2, 2), 27)
+    assert e.value.status == j3d.J3D_EINVAL
+
+
+def test_block_extents_rules():
+    nb, ext = j3d.j3d_block_extents(j3d.Problem((10, 7, 5), None, auto_parts=6))
+    assert nb == (3, 2, 1)
+    assert ext == ([4, 3, 3], [4, 3], [5])
+    nb, ext = j3d.j3d_block_extents(j3d.Problem((12, 6, 9), (3, 2, 3)))
+    assert ext == ([4, 4, 4], [3, 3], [3, 3, 3])
+    nb, ext = j3d.j3d_block_extents(j3d.Problem((10, 6, 9), (3, 1, 2), split=([1, 2, 7], None, [8, 1])))
+    assert ext == ([1, 2, 7], [6], [8, 1])
+
+
+@pytest.mark.parametrize("kwargs", [
+    dict(n=(0, 4, 4)),
+    dict(n=(4, 4, 4), nblk=(5, 1, 1)),
+    dict(n=(10, 4, 4), nblk=(3, 1, 1)),                       # even split does not divide
+    dict(n=(10, 4, 4), nblk=(2, 1, 1), split=([3, 6], None, None)),  # sum mismatch
+    dict(n=(10, 4, 4), nblk=(2, 1, 1), split=([0, 10], None, None)),  # empty block
+    dict(n=(4, 4, 4), nblk=(1, 0, 1)),
+    dict(n=(4, 4, 4), bc=(0, 0, float("nan"), 0, 0, 0)),
+    dict(n=(4, 4, 4), bc=(0, 0, 0, float("inf"), 0, 0)),
+    dict(n=(2 ** 31, 1, 1)),
+    dict(n=(4096, 4096, 4096)),                              # one block beyond 2^31 cells
+])
+def test_invalid_problems_are_rejected(kwargs):
+    p = j3d.Problem(kwargs.pop("n"), **kwargs)
+    for fn in (j3d.j3d_arena_bytes, j3d.j3d_field_bytes, j3d.j3d_block_extents):
+        with pytest.raises(j3d.J3DError) as e:
+            fn(p)
+        assert e.value.status == j3d.J3D_EINVAL
+    assert j3d.j3d_last_error() != ""
+
+
+def test_arena_covers_fields_and_grows():
+    small = j3d.Problem((64, 64, 64))
+    over = j3d.Problem((64, 64, 64), (4, 4, 4))
+    for p in (small, over):
+        assert j3d.j3d_arena_bytes(p) > j3d.j3d_field_bytes(p) >= 2 * 8 * 64 ** 3
+        assert j3d.j3d_arena_bytes(p) % 4096 == 0
+    assert j3d.j3d_arena_bytes(over) > j3d.j3d_arena_bytes(small)
+    # 512^3 as 8^3 blocks: two fields of 1.07 GB plus halo storage (~9% at 64^3 blocks)
+    cfg1 = j3d.Problem((512, 512, 512), (8, 8, 8))
+    fb = j3d.j3d_field_bytes(cfg1)
+    assert 2 * 8 * 512 ** 3 < fb < 1.1 * 2 * 8 * 512 ** 3
+    assert j3d.j3d_batch_arena_bytes([small, over]) > j3d.j3d_arena_bytes(over)
+
+
+def test_variant_table():
+    vs = j3d.variants()
+    assert len(vs) >= 8
+    for tx, ty, threads in vs:
+        assert threads % 64 == 0 and threads <= 1024
+        assert tx in (32, 64, 128, 256) and ty >= 16
+    with pytest.raises(j3d.J3DError):
+        j3d.j3d_variant_info(len(vs))
+
+
+def test_pool_sizing_host_only():
+    p = j3d.Problem((32, 40, 48))
+    b = j3d.j3d_pool_request_bytes(p)
+    assert b >= 2 * 8 * 32 * 40 * 48 and b % 4096 == 0
+    assert j3d.j3d_pool_overhead_bytes(256) > 0
+    with pytest.raises(j3d.J3DError) as e:
+        j3d.j3d_pool_request_bytes(j3d.Problem((64, 64, 64), (2, 1, 1)))
+    assert e.value.status == j3d.J3D_EINVAL
+    with pytest.raises(j3d.J3DError):
+        j3d.j3d_pool_overhead_bytes(0)
+
+
+def test_create_validates_before_device_work():
+    p = j3d.Problem((16, 16, 16), (2, 2, 2))
+    need = j3d.j3d_arena_bytes(p)
+    with pytest.raises(j3d.J3DError) as e:
+        j3d.j3d_create(p, 0, need, 0)                 # NULL arena
+    assert e.value.status == j3d.J3D_EINVAL
+    with pytest.raises(j3d.J3DError) as e:
+        j3d.j3d_create(p, 0x10000 + 8, need, 0)       # misaligned
+    assert e.value.status == j3d.J3D_EINVAL
+    with pytest.raises(j3d.J3DError) as e:
+        j3d.j3d_create(p, 0x10000, need - 4096, 0)    # arena too small
+    assert e.value.status == j3d.J3D_ENOMEM
+    with pytest.raises(j3d.J3DError) as e:
+        j3d.j3d_batch_create([p], [-1], 0x10000, 1 << 40, 0)
+    assert e.value.status == j3d.J3D_EINVAL
+
+
+def _no_gpu_here():
+    if os.path.exists("/dev/kfd"):
+        return False
+    try:
+        import torch
+        return torch.cuda.device_count() == 0
+    except Exception:
+        return True
+
+
+@pytest.mark.skipif(not _no_gpu_here(), reason="only meaningful where no GPU is present")
+def test_create_without_device_is_edevice():
+    p = j3d.Problem((8, 8, 8))
+    with pytest.raises(j3d.J3DError) as e:
+        j3d.j3d_create(p, 0x10000, j3d.j3d_arena_bytes(p), 0)
+    assert e.value.status == j3d.J3D_EDEVICE
+    with pytest.raises(j3d.J3DError) as e:
+        j3d.j3d_device_cus()
+    assert e.value.status == j3d.J3D_EDEVICE
