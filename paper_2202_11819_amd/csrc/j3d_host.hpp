@@ -80,10 +80,13 @@ uint64_t count_tiles(const Plan &plan, int variant, int zchunk);
 // Validates a tune against a plan; fills the effective z-chunk.
 j3d_status check_tune(const Plan &plan, const j3d_tune *t, int *zchunk_eff);
 
-// Ghosted cells of one block's field (one parity).
+// Row stride of a block's field in doubles: rows start on 128-byte lines.
+inline int64_t row_pitch(int64_t ex) { return ex >= 16 ? (ex + 15) / 16 * 16 : ex; }
+
+// Cells of one block's field (one parity), halos and row padding included.
 inline int64_t block_field_cells(int64_t ex, int64_t ey, int64_t ez)
 {
-    return ex * (ey + 2) * (ez + 2);
+    return row_pitch(ex) * (ey + 2) * (ez + 2);
 }
 
 inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }

@@ -4,12 +4,14 @@
 // two iterates (parity 0 and 1; Sec. III-C keeps two copies of the block and
 // swaps their roles every iteration):
 //
-//   field  F[p][b]: (ez+2) planes x (ey+2) rows x ex doubles, x fastest.
-//          Plane 0 and plane ez+1 hold the z- / z+ halos, row 0 and row ey+1
-//          of every plane hold the y- / y+ halos; interior cell (x, y, z) sits
-//          at ((z+1)*(ey+2) + (y+1))*ex + x.  Rows are dense (no x ghosts), so
-//          a row of the interior and a y- or z-halo row are the same contiguous
-//          ex doubles; edge rows of the halo planes are never read.
+//   field  F[p][b]: (ez+2) planes x (ey+2) rows x pitch doubles, x fastest,
+//          pitch = ex rounded up to a multiple of 16 (a 128-byte cache line)
+//          when ex >= 16, else ex.  Plane 0 and plane ez+1 hold the z- / z+
+//          halos, row 0 and row ey+1 of every plane hold the y- / y+ halos;
+//          interior cell (x, y, z) sits at ((z+1)*(ey+2) + (y+1))*pitch + x.
+//          Rows carry no x ghosts, so a row of the interior and a y- or z-halo
+//          row are the same contiguous ex doubles; edge rows of the halo
+//          planes and the row padding are never read.
 //   x-halo X[p][b]: two arrays of ey*ez doubles (x- then x+), y fastest.  The
 //          x-halos live apart from the rows so that a neighbour writes them as
 //          contiguous runs instead of one double per row.
@@ -38,7 +40,8 @@ struct BlockDesc {          // 128 bytes, read by kernels through scalar loads
     int32_t prob;           // index of the owning problem in the problem table
     int32_t nbr[6];         // neighbour block per face (table index) or -1
     int32_t org[3];         // global coordinates of the block's first cell
-    int32_t pad[7];
+    int32_t pitch;          // row stride of the field in doubles: ex rounded up to 16 (128 B)
+    int32_t pad[6];
 };
 static_assert(sizeof(BlockDesc) == 128, "BlockDesc layout");
 

@@ -70,8 +70,52 @@ __device__ __forceinline__ int xcd_remap(int i, int n)
 }
 
 // ---- the sweep ----------------------------------------------------------------
+//
+// Addressing: every global access is a uniform (scalar) 64-bit base pointer
+// for the current plane plus a 32-bit per-lane byte offset inside that plane,
+// so the hardware's scalar-base + vector-offset form is used and each thread
+// keeps one offset per row instead of one 64-bit address per row and plane.
 
-template <int TX, int NTY, int RY>
+#ifndef J3D_NT_LOAD
+#define J3D_NT_LOAD 1   // interior cells are read once per sweep: stream them
+#endif
+#ifndef J3D_NT_STORE
+#define J3D_NT_STORE 1  // the next iterate is not read again within the sweep
+#endif
+
+// Raw buffer accesses: a 128-bit resource (base, byte range) in scalar
+// registers plus a 32-bit per-lane byte offset.  Every streaming access of the
+// sweep goes through a resource that spans exactly one plane (or one halo
+// row), so an offset outside it reads 0 and drops the store instead of
+// touching other memory.
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+constexpr int kRsrcWord3 = 0x00020000;  // gfx9-family raw buffer, 32-bit elements
+constexpr int kAuxNT = 2;               // non-temporal (streaming) cache policy
+constexpr int kAuxLoad = J3D_NT_LOAD ? kAuxNT : 0;
+constexpr int kAuxStore = J3D_NT_STORE ? kAuxNT : 0;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, uint64_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0,
+                                             (int)(bytes > 0x7fffffffull ? 0x7fffffffull : bytes),
+                                             kRsrcWord3);
+}
+
+template <int AUX>
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, AUX));
+}
+
+__device__ __forceinline__ void st_cell(char *p, double v) { *reinterpret_cast<double *>(p) = v; }
+
+template <int AUX>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(i32x2, v), r, (int)off, 0, AUX);
+}
+
+template <int TX, int NTY, int RY, int PF>
 struct Shape {
     static constexpr int TY = NTY * RY;   // tile rows
     static constexpr int NT = TX * NTY;   // threads
@@ -80,149 +124,96 @@ struct Shape {
     static constexpr int LDS = 2 * LX * LY;
     static_assert(NT >= 2 * TX + 2 * TY, "every halo cell of a plane needs a loader thread");
     static_assert(NT % 64 == 0, "whole waves");
+    static_assert(PF == 1 || PF == 2, "prefetch depth");
 };
 
-template <int TX, int NTY, int RY>
-__device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, double *sm, double *red)
+// Uniform description of one tile (lives in scalar registers).
+struct TileGeo {
+    const char *cur;   // input field, byte address of plane index 0
+    char *nxt;         // output field
+    char *dxm, *dxp;   // neighbours' x-halo arrays of the next iterate (null: none)
+    char *dym, *dyp;   // neighbours' y-halo row 0 / ey+1 at plane index 0 (null: none)
+    char *dzm, *dzp;   // neighbours' z-halo plane (null: none)
+    uint64_t psb;      // plane stride of this block's field, bytes
+    uint64_t psym, psyp;  // plane strides of the y neighbours, bytes
+    int ex, ey, ez, pitch;  // pitch: row stride in doubles (>= ex)
+    int x0, y0, z0, nxv, nyv, nzv;
+    bool fused, want_res;
+};
+
+template <int TX, int NTY, int RY, int PF, bool FULL>
+__device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *__restrict__ hsrc0,
+                                               uint64_t hstep, int hl, double *sm)
 {
-    using S = Shape<TX, NTY, RY>;
-    const BlockDesc *__restrict__ B = a.blocks + tl.block;
-    const ProbDesc *__restrict__ P = a.probs + B->prob;
-
-    int p;
-    bool want_res;
-    if (a.flags & SW_MULTI) {
-        const int64_t t = P->base + a.step;
-        if (t >= P->limit) return;  // uniform over the workgroup
-        p = (int)(t & 1);
-        const int64_t t1 = t + 1;
-        want_res = ((P->flags & PF_RES_LAST) && t1 == P->limit) ||
-                   (P->check_every > 0 && t1 % P->check_every == 0);
-    } else {
-        p = a.parity;
-        want_res = (a.flags & SW_RES) != 0;
-    }
-    const bool fused = (a.flags & SW_FUSED) != 0;
-
-    const int ex = B->ext[0], ey = B->ext[1], ez = B->ext[2];
-    const int PS = (ey + 2) * ex;  // plane stride of the field
-    const double *__restrict__ cur = a.base + B->off[p];
-    double *__restrict__ nxt = a.base + B->off[p ^ 1];
-
-    const int x0 = tl.tx * TX, y0 = tl.ty * S::TY, z0 = tl.tz * a.zchunk;
-    const int nxv = min(TX, ex - x0), nyv = min(S::TY, ey - y0), nzv = min(a.zchunk, ez - z0);
-
+    using S = Shape<TX, NTY, RY, PF>;
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    const int x = x0 + tx;
-    const bool vx = tx < nxv;
-
-    // Destinations of this block's face values in the neighbours' halo
-    // storage of the next iterate (null: global boundary or unfused).
-    double *dxm = nullptr, *dxp = nullptr, *dym = nullptr, *dyp = nullptr, *dzm = nullptr,
-           *dzp = nullptr;
-    int psym = 0, psyp = 0;
-    if (fused) {
-        const int q = p ^ 1;
-        if (B->nbr[0] >= 0) dxm = a.base + a.blocks[B->nbr[0]].xoff[q] + (int64_t)ey * ez;
-        if (B->nbr[1] >= 0) dxp = a.base + a.blocks[B->nbr[1]].xoff[q];
-        if (B->nbr[2] >= 0) {
-            const BlockDesc *N = a.blocks + B->nbr[2];
-            psym = (N->ext[1] + 2) * ex;
-            dym = a.base + N->off[q] + (int64_t)(N->ext[1] + 1) * ex;
-        }
-        if (B->nbr[3] >= 0) {
-            const BlockDesc *N = a.blocks + B->nbr[3];
-            psyp = (N->ext[1] + 2) * ex;
-            dyp = a.base + N->off[q];
-        }
-        if (B->nbr[4] >= 0) {
-            const BlockDesc *N = a.blocks + B->nbr[4];
-            dzm = a.base + N->off[q] + (int64_t)(N->ext[2] + 1) * PS;
-        }
-        if (B->nbr[5] >= 0) dzp = a.base + a.blocks[B->nbr[5]].off[q];
-    }
-
-    // This thread's cells: rows y0 + ty + NTY*r of column x.
+    const int ex = g.ex;
+    const uint32_t rowb = (uint32_t)g.pitch * 8u;
+    // Lanes outside a ragged tile load a clamped (valid) cell and never store.
+    const int cx = FULL ? tx : min(tx, g.nxv - 1);
     bool vr[RY];
-    int col[RY];  // field offset of (x, y_r) in plane index 0
+    uint32_t off[RY];  // byte offset of this thread's cell of row r inside a plane
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         const int ly = ty + NTY * r;
-        vr[r] = vx && ly < nyv;
-        col[r] = (y0 + ly + 1) * ex + x;
+        vr[r] = FULL ? true : (tx < g.nxv && ly < g.nyv);
+        const int cy = FULL ? ly : min(ly, g.nyv - 1);
+        off[r] = (uint32_t)(g.y0 + cy + 1) * rowb + (uint32_t)(g.x0 + cx) * 8u;
     }
+    const int x = g.x0 + tx;
+    const bool wxm = g.dxm && x == 0, wxp = g.dxp && x == ex - 1;
+    const uint32_t xo = (uint32_t)x * 8u;
+    const uint64_t psb = g.psb;
 
-    // Halo loader role: one ring cell of the LDS plane per thread.
-    int hl = -1;
-    const double *__restrict__ hsrc = nullptr;
-    int hstep = 0;
-    if (tid < 2 * TX) {
-        const int side = tid / TX, xx = tid % TX;
-        if (xx < nxv) {
-            const int row = side ? (y0 + nyv) : (y0 - 1);  // a halo row when at the block edge
-            hsrc = cur + PS + (row + 1) * ex + x0 + xx;
-            hstep = PS;
-            hl = (side ? (nyv + 1) : 0) * S::LX + xx + 1;
-        }
-    } else if (tid < 2 * TX + 2 * S::TY) {
-        const int u = tid - 2 * TX;
-        const int side = u / S::TY, yy = u % S::TY;
-        if (yy < nyv) {
-            const int y = y0 + yy;
-            if (side == 0) {
-                if (x0 == 0) {
-                    hsrc = a.base + B->xoff[p] + y;
-                    hstep = ey;
-                } else {
-                    hsrc = cur + PS + (y + 1) * ex + x0 - 1;
-                    hstep = PS;
-                }
-                hl = (yy + 1) * S::LX;
-            } else {
-                const int xr = x0 + nxv;
-                if (xr == ex) {
-                    hsrc = a.base + B->xoff[p] + (int64_t)ey * ez + y;
-                    hstep = ey;
-                } else {
-                    hsrc = cur + PS + (y + 1) * ex + xr;
-                    hstep = PS;
-                }
-                hl = (yy + 1) * S::LX + nxv + 1;
-            }
-        }
-    }
-
-    double zm[RY], c[RY], zp[RY], zq[RY];
+    double zm[RY], c[RY], zp[RY], zq[RY], zr[RY];
+    {
+        const char *pk = g.cur + (uint64_t)g.z0 * psb;  // plane index z0 = interior plane z0-1
+        const __amdgpu_buffer_rsrc_t r0 = rsrc(pk, psb), r1 = rsrc(pk + psb, psb), r2 = rsrc(pk + 2 * psb, psb);
 #pragma unroll
-    for (int r = 0; r < RY; ++r) {
-        zm[r] = c[r] = zp[r] = zq[r] = 0.0;
-        if (vr[r]) {
-            const double *q = cur + col[r];
-            zm[r] = q[z0 * PS];            // plane z0-1 (the z- halo when z0 == 0)
-            c[r] = q[(z0 + 1) * PS];       // plane z0
-            zp[r] = q[(z0 + 2) * PS];      // plane z0+1 (the z+ halo when z0 == ez-1)
+        for (int r = 0; r < RY; ++r) {
+            zm[r] = bload<kAuxLoad>(r0, off[r]);
+            c[r] = bload<kAuxLoad>(r1, off[r]);
+            zp[r] = bload<kAuxLoad>(r2, off[r]);
+            zq[r] = zr[r] = 0.0;
+        }
+        if (PF == 2 && g.nzv > 1) {
+            const __amdgpu_buffer_rsrc_t r3 = rsrc(pk + 3 * psb, psb);
+#pragma unroll
+            for (int r = 0; r < RY; ++r) zq[r] = bload<kAuxLoad>(r3, off[r]);
         }
     }
-    double h = (hl >= 0) ? hsrc[(int64_t)z0 * hstep] : 0.0;
+    const double *hp = hsrc0 + (uint64_t)g.z0 * hstep;
+    double h = hl >= 0 ? *hp : 0.0;
     double rmax = 0.0;
 
-    for (int kk = 0; kk < nzv; ++kk) {
-        const int k = z0 + kk;
-        const bool more = kk + 1 < nzv;
-        double hn = 0.0;
-        if (more) {
+    for (int kk = 0; kk < g.nzv; ++kk) {
+        const int k = g.z0 + kk;
+        // issue the loads of later planes before this plane's work
+        if (PF == 1) {
+            if (kk + 1 < g.nzv) {
+                const __amdgpu_buffer_rsrc_t rn = rsrc(g.cur + (uint64_t)(k + 3) * psb, psb);
 #pragma unroll
-            for (int r = 0; r < RY; ++r)
-                if (vr[r]) zq[r] = cur[col[r] + (k + 3) * PS];  // plane k+2
-            if (hl >= 0) hn = hsrc[(int64_t)(k + 1) * hstep];
+                for (int r = 0; r < RY; ++r) zq[r] = bload<kAuxLoad>(rn, off[r]);
+            }
+        } else {
+            if (kk + 2 < g.nzv) {
+                const __amdgpu_buffer_rsrc_t rn = rsrc(g.cur + (uint64_t)(k + 4) * psb, psb);
+#pragma unroll
+                for (int r = 0; r < RY; ++r) zr[r] = bload<kAuxLoad>(rn, off[r]);
+            }
         }
+        double hn = 0.0;
+        if (hl >= 0 && kk + 1 < g.nzv) hn = hp[(uint64_t)(kk + 1) * hstep];
+
         double *L = sm + (kk & 1) * (S::LX * S::LY);
 #pragma unroll
         for (int r = 0; r < RY; ++r)
             if (vr[r]) L[(ty + NTY * r + 1) * S::LX + tx + 1] = c[r];
         if (hl >= 0) L[hl] = h;
         __syncthreads();
+
+        const __amdgpu_buffer_rsrc_t ro = rsrc(g.nxt + (uint64_t)(k + 1) * psb, psb);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             if (!vr[r]) continue;
@@ -235,17 +226,19 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
             s += zm[r];
             s += zp[r];
             const double v = s * kW;
-            nxt[col[r] + (k + 1) * PS] = v;
-            if (fused) {
-                const int y = y0 + ty + NTY * r;
-                if (x == 0 && dxm) dxm[y + ey * k] = v;
-                if (x == ex - 1 && dxp) dxp[y + ey * k] = v;
-                if (y == 0 && dym) dym[(k + 1) * psym + x] = v;
-                if (y == ey - 1 && dyp) dyp[(k + 1) * psyp + x] = v;
-                if (k == 0 && dzm) dzm[(y + 1) * ex + x] = v;
-                if (k == ez - 1 && dzp) dzp[(y + 1) * ex + x] = v;
+            bstore<kAuxStore>(ro, off[r], v);
+            if (g.fused) {
+                // this block's new face values, straight into the neighbours'
+                // halo storage of the next iterate (rare lanes / planes)
+                const int y = g.y0 + ty + NTY * r;
+                if (wxm) st_cell(g.dxm + ((uint64_t)k * g.ey + y) * 8u, v);
+                if (wxp) st_cell(g.dxp + ((uint64_t)k * g.ey + y) * 8u, v);
+                if (g.dym && y == 0) st_cell(g.dym + (uint64_t)(k + 1) * g.psym + xo, v);
+                if (g.dyp && y == g.ey - 1) st_cell(g.dyp + (uint64_t)(k + 1) * g.psyp + xo, v);
+                if (g.dzm && k == 0) st_cell(g.dzm + off[r], v);
+                if (g.dzp && k == g.ez - 1) st_cell(g.dzp + off[r], v);
             }
-            if (want_res) {
+            if (g.want_res) {
                 const double d = fabs(v - c[r]);
                 rmax = d > rmax ? d : rmax;
             }
@@ -255,69 +248,192 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
             zm[r] = c[r];
             c[r] = zp[r];
             zp[r] = zq[r];
+            if (PF == 2) zq[r] = zr[r];
         }
         h = hn;
     }
+    return rmax;
+}
 
-    if (want_res) {
+template <int TX, int NTY, int RY, int PF>
+__device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, double *sm, double *red)
+{
+    using S = Shape<TX, NTY, RY, PF>;
+    const BlockDesc *__restrict__ B = a.blocks + tl.block;
+    const ProbDesc *__restrict__ P = a.probs + B->prob;
+
+    TileGeo g;
+    int p;
+    if (a.flags & SW_MULTI) {
+        const int64_t t = P->base + a.step;
+        if (t >= P->limit) return;  // uniform over the workgroup
+        p = (int)(t & 1);
+        const int64_t t1 = t + 1;
+        g.want_res = ((P->flags & PF_RES_LAST) && t1 == P->limit) ||
+                     (P->check_every > 0 && t1 % P->check_every == 0);
+    } else {
+        p = a.parity;
+        g.want_res = (a.flags & SW_RES) != 0;
+    }
+    g.fused = (a.flags & SW_FUSED) != 0;
+    g.ex = B->ext[0];
+    g.ey = B->ext[1];
+    g.ez = B->ext[2];
+    g.pitch = B->pitch;
+    const int ex = g.ex, ey = g.ey, ez = g.ez, pitch = g.pitch;
+    g.psb = (uint64_t)(ey + 2) * pitch * 8u;
+    char *base = reinterpret_cast<char *>(a.base);
+    g.cur = base + B->off[p] * 8;
+    g.nxt = base + B->off[p ^ 1] * 8;
+    // Balanced tiling: a block axis of e cells is cut into n = ceil(e / T)
+    // tiles of near-equal length (each <= T), so no tile is a thin remainder.
+    {
+        const int ntx = (ex + TX - 1) / TX, nty = (ey + S::TY - 1) / S::TY;
+        const int ntz = (ez + a.zchunk - 1) / a.zchunk;
+        g.x0 = (int)((int64_t)tl.tx * ex / ntx);
+        g.y0 = (int)((int64_t)tl.ty * ey / nty);
+        g.z0 = (int)((int64_t)tl.tz * ez / ntz);
+        g.nxv = (int)((int64_t)(tl.tx + 1) * ex / ntx) - g.x0;
+        g.nyv = (int)((int64_t)(tl.ty + 1) * ey / nty) - g.y0;
+        g.nzv = (int)((int64_t)(tl.tz + 1) * ez / ntz) - g.z0;
+    }
+
+    g.dxm = g.dxp = g.dym = g.dyp = g.dzm = g.dzp = nullptr;
+    g.psym = g.psyp = 0;
+    if (g.fused) {
+        const int q = p ^ 1;
+        if (B->nbr[0] >= 0) g.dxm = base + (a.blocks[B->nbr[0]].xoff[q] + (int64_t)ey * ez) * 8;
+        if (B->nbr[1] >= 0) g.dxp = base + a.blocks[B->nbr[1]].xoff[q] * 8;
+        if (B->nbr[2] >= 0) {
+            const BlockDesc *N = a.blocks + B->nbr[2];
+            g.psym = (uint64_t)(N->ext[1] + 2) * pitch * 8u;
+            g.dym = base + (N->off[q] + (int64_t)(N->ext[1] + 1) * pitch) * 8;
+        }
+        if (B->nbr[3] >= 0) {
+            const BlockDesc *N = a.blocks + B->nbr[3];
+            g.psyp = (uint64_t)(N->ext[1] + 2) * pitch * 8u;
+            g.dyp = base + N->off[q] * 8;
+        }
+        if (B->nbr[4] >= 0) {
+            const BlockDesc *N = a.blocks + B->nbr[4];
+            g.dzm = base + N->off[q] * 8 + (uint64_t)(N->ext[2] + 1) * g.psb;
+        }
+        if (B->nbr[5] >= 0) g.dzp = base + a.blocks[B->nbr[5]].off[q] * 8;
+    }
+
+    // Halo loader role: one ring cell of the LDS plane per thread.  hsrc0
+    // points at plane index 0's value; plane k adds k*hstep doubles.
+    const int tid = threadIdx.x;
+    int hl = -1;
+    const double *hsrc0 = a.base;
+    uint64_t hstep = 0;
+    const uint64_t ps = (uint64_t)(ey + 2) * pitch;
+    const double *curd = a.base + B->off[p];
+    if (tid < 2 * TX) {
+        const int side = tid / TX, xx = tid % TX;
+        if (xx < g.nxv) {
+            const int row = side ? (g.y0 + g.nyv) : (g.y0 - 1);  // a halo row at the block edge
+            hsrc0 = curd + ps + (uint64_t)(row + 1) * pitch + g.x0 + xx;
+            hstep = ps;
+            hl = (side ? (g.nyv + 1) : 0) * S::LX + xx + 1;
+        }
+    } else if (tid < 2 * TX + 2 * S::TY) {
+        const int u = tid - 2 * TX;
+        const int side = u / S::TY, yy = u % S::TY;
+        if (yy < g.nyv) {
+            const int y = g.y0 + yy;
+            if (side == 0) {
+                if (g.x0 == 0) {
+                    hsrc0 = a.base + B->xoff[p] + y;
+                    hstep = ey;
+                } else {
+                    hsrc0 = curd + ps + (uint64_t)(y + 1) * pitch + g.x0 - 1;
+                    hstep = ps;
+                }
+                hl = (yy + 1) * S::LX;
+            } else {
+                const int xr = g.x0 + g.nxv;
+                if (xr == ex) {
+                    hsrc0 = a.base + B->xoff[p] + (int64_t)ey * ez + y;
+                    hstep = ey;
+                } else {
+                    hsrc0 = curd + ps + (uint64_t)(y + 1) * pitch + xr;
+                    hstep = ps;
+                }
+                hl = (yy + 1) * S::LX + g.nxv + 1;
+            }
+        }
+    }
+
+    const bool full = g.nxv == TX && g.nyv == S::TY;
+    const double rmax = full ? sweep_planes<TX, NTY, RY, PF, true>(g, hsrc0, hstep, hl, sm)
+                             : sweep_planes<TX, NTY, RY, PF, false>(g, hsrc0, hstep, hl, sm);
+
+    if (g.want_res) {
         // max over the workgroup, then one atomic per tile; the maximum of
         // non-negative doubles orders like their bit patterns, so the result
         // is exact and independent of the order of arrival.
+        double m = rmax;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
-            const double t = __shfl_xor(rmax, o);
-            rmax = t > rmax ? t : rmax;
+            const double t = __shfl_xor(m, o);
+            m = t > m ? t : m;
         }
-        if ((tid & 63) == 0) red[tid >> 6] = rmax;
+        if ((tid & 63) == 0) red[tid >> 6] = m;
         __syncthreads();
         if (tid == 0) {
-            double m = 0.0;
-            for (int w = 0; w < S::NT / 64; ++w) m = red[w] > m ? red[w] : m;
-            atomic_max_agent(a.res + P->res_slot, (unsigned long long)__double_as_longlong(m));
+            double w = 0.0;
+            for (int i = 0; i < S::NT / 64; ++i) w = red[i] > w ? red[i] : w;
+            atomic_max_agent(a.res + P->res_slot, (unsigned long long)__double_as_longlong(w));
         }
     }
-    __syncthreads();  // the next tile of a persistent workgroup reuses the LDS
 }
 
-template <int TX, int NTY, int RY>
+template <int TX, int NTY, int RY, int PF>
 __global__ __launch_bounds__(TX *NTY) void sweep_kernel(SweepArgs a)
 {
-    using S = Shape<TX, NTY, RY>;
+    using S = Shape<TX, NTY, RY, PF>;
+    __shared__ double sm[S::LDS];
+    __shared__ double red[S::NT / 64];
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    sweep_tile<TX, NTY, RY, PF>(a, a.tiles[a.tile_begin + t], sm, red);
+}
+
+// Persistent form: a grid of a few workgroups per compute unit; per-XCD
+// queues over contiguous tile ranges; a workgroup drains its own XCD's
+// queue, then helps the others.
+template <int TX, int NTY, int RY, int PF>
+__global__ __launch_bounds__(TX *NTY) void sweep_kernel_persistent(SweepArgs a)
+{
+    using S = Shape<TX, NTY, RY, PF>;
     __shared__ double sm[S::LDS];
     __shared__ double red[S::NT / 64];
     __shared__ int next_tile;
-
-    if (a.flags & SW_PERSIST) {
-        // Per-XCD queues over contiguous tile ranges; a workgroup drains its
-        // own XCD's queue, then helps the others.
-        const int xcd = blockIdx.x % kXcds;
-        for (int qi = 0; qi < kXcds; ++qi) {
-            const int q = (xcd + qi) % kXcds;
-            const int beg = (int)((int64_t)a.tile_count * q / kXcds);
-            const int end = (int)((int64_t)a.tile_count * (q + 1) / kXcds);
-            for (;;) {
-                if (threadIdx.x == 0)
-                    next_tile = beg + (int)atomic_add_agent(a.queue + a.queue_slot * kXcds + q, 1u);
-                __syncthreads();
-                const int t = next_tile;
-                __syncthreads();
-                if (t >= end) break;
-                sweep_tile<TX, NTY, RY>(a, a.tiles[a.tile_begin + t], sm, red);
-            }
+    const int xcd = blockIdx.x % kXcds;
+    for (int qi = 0; qi < kXcds; ++qi) {
+        const int q = (xcd + qi) % kXcds;
+        const int beg = (int)((int64_t)a.tile_count * q / kXcds);
+        const int end = (int)((int64_t)a.tile_count * (q + 1) / kXcds);
+        for (;;) {
+            if (threadIdx.x == 0)
+                next_tile = beg + (int)atomic_add_agent(a.queue + a.queue_slot * kXcds + q, 1u);
+            __syncthreads();
+            const int t = next_tile;
+            __syncthreads();
+            if (t >= end) break;
+            sweep_tile<TX, NTY, RY, PF>(a, a.tiles[a.tile_begin + t], sm, red);
+            __syncthreads();  // the next tile reuses the LDS
         }
-        // Re-arm the other half of the counters for the next persistent launch.
-        if (blockIdx.x == 0 && threadIdx.x < kXcds)
-            atomic_store_agent(a.queue + (a.queue_slot ^ 1) * kXcds + threadIdx.x, 0u);
-    } else {
-        const int t = xcd_remap(blockIdx.x, gridDim.x);
-        sweep_tile<TX, NTY, RY>(a, a.tiles[a.tile_begin + t], sm, red);
     }
+    // Re-arm the other half of the counters for the next persistent launch.
+    if (blockIdx.x == 0 && threadIdx.x < kXcds)
+        atomic_store_agent(a.queue + (a.queue_slot ^ 1) * kXcds + threadIdx.x, 0u);
 }
 
 // ---- unfused halo kernels (one thread per cell of the largest face) ----------
 
 struct FaceGeom {
-    int ex, ey, ez, PS, fx, fy, fz;
+    int ex, ey, ez, pitch, PS, fx, fy, fz;
     int64_t o[6];  // offsets of the six faces inside S[b] / R[b]
 };
 
@@ -327,7 +443,8 @@ __device__ __forceinline__ FaceGeom face_geom(const BlockDesc &B)
     g.ex = B.ext[0];
     g.ey = B.ext[1];
     g.ez = B.ext[2];
-    g.PS = (g.ey + 2) * g.ex;
+    g.pitch = B.pitch;
+    g.PS = (g.ey + 2) * g.pitch;
     g.fx = g.ey * g.ez;
     g.fy = g.ex * g.ez;
     g.fz = g.ex * g.ey;
@@ -347,16 +464,16 @@ __device__ __forceinline__ int64_t face_cell(const FaceGeom &g, int f, int i, bo
 {
     if (f < 2) {
         const int y = i % g.ey, z = i / g.ey;
-        return (int64_t)(z + 1) * g.PS + (y + 1) * g.ex + (f == 0 ? 0 : g.ex - 1);
+        return (int64_t)(z + 1) * g.PS + (int64_t)(y + 1) * g.pitch + (f == 0 ? 0 : g.ex - 1);
     }
     if (f < 4) {
         const int x = i % g.ex, z = i / g.ex;
         const int row = interior ? (f == 2 ? 1 : g.ey) : (f == 2 ? 0 : g.ey + 1);
-        return (int64_t)(z + 1) * g.PS + row * g.ex + x;
+        return (int64_t)(z + 1) * g.PS + (int64_t)row * g.pitch + x;
     }
     const int x = i % g.ex, y = i / g.ex;
     const int plane = interior ? (f == 4 ? 1 : g.ez) : (f == 4 ? 0 : g.ez + 1);
-    return (int64_t)plane * g.PS + (y + 1) * g.ex + x;
+    return (int64_t)plane * g.PS + (int64_t)(y + 1) * g.pitch + x;
 }
 
 __device__ __forceinline__ int face_size(const FaceGeom &g, int f)
@@ -433,15 +550,20 @@ __global__ __launch_bounds__(256) void init_kernel(double *base, const BlockDesc
     const double qnan = __builtin_nan("");
     for (int bb = blockIdx.y; bb < nblocks; bb += gridDim.y) {
         const BlockDesc &B = blocks[block_begin + bb];
-        const int ex = B.ext[0], ey = B.ext[1], ez = B.ext[2];
-        const int64_t cells = (int64_t)ex * (ey + 2) * (ez + 2);
+        const int ex = B.ext[0], ey = B.ext[1], ez = B.ext[2], pitch = B.pitch;
+        const int64_t cells = (int64_t)pitch * (ey + 2) * (ez + 2);
         double *F0 = base + B.off[0];
         double *F1 = base + B.off[1];
         double *Fp = parity ? F1 : F0;
         const int64_t stride = (int64_t)gridDim.x * blockDim.x;
         for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < cells; idx += stride) {
-            const int x = (int)(idx % ex);
-            const int64_t rr = idx / ex;
+            const int x = (int)(idx % pitch);
+            const int64_t rr = idx / pitch;
+            if (x >= ex) {  // row padding: never read as data
+                F0[idx] = 0.0;
+                F1[idx] = 0.0;
+                continue;
+            }
             const int yy = (int)(rr % (ey + 2)), zz = (int)(rr / (ey + 2));
             const bool oy = (yy == 0 || yy == ey + 1), oz = (zz == 0 || zz == ez + 1);
             if (!oy && !oz) {
@@ -489,8 +611,8 @@ __device__ __forceinline__ int64_t dense_to_block(const BlockDesc *blocks, int b
     const int by = m.my[2 * j], ly = m.my[2 * j + 1];
     const int bz = m.mz[2 * k], lz = m.mz[2 * k + 1];
     const BlockDesc &B = blocks[block_base + bx + m.nb0 * (by + m.nb1 * bz)];
-    const int ex = B.ext[0], ey = B.ext[1];
-    return B.off[parity] + (int64_t)(lz + 1) * (ey + 2) * ex + (int64_t)(ly + 1) * ex + lx;
+    const int pitch = B.pitch, ey = B.ext[1];
+    return B.off[parity] + (int64_t)(lz + 1) * (ey + 2) * pitch + (int64_t)(ly + 1) * pitch + lx;
 }
 
 __global__ __launch_bounds__(256) void scatter_kernel(double *base, const BlockDesc *blocks,
@@ -550,16 +672,16 @@ __global__ __launch_bounds__(256) void set_face_kernel(double *base, const Block
             ly = m.my[2 * j + 1];
         }
         const BlockDesc &B = blocks[block_base + bx + m.nb0 * (by + m.nb1 * bz)];
-        const int ex = B.ext[0], ey = B.ext[1], ez = B.ext[2];
-        const int64_t PS = (int64_t)(ey + 2) * ex;
+        const int pitch = B.pitch, ey = B.ext[1], ez = B.ext[2];
+        const int64_t PS = (int64_t)(ey + 2) * pitch;
         const double v = src[g];
         for (int q = 0; q < 2; ++q) {
             if (axis == 0) {
                 base[B.xoff[q] + (face == 1 ? (int64_t)ey * ez : 0) + ly + (int64_t)ey * lz] = v;
             } else if (axis == 1) {
-                base[B.off[q] + (lz + 1) * PS + (int64_t)(face == 2 ? 0 : ey + 1) * ex + lx] = v;
+                base[B.off[q] + (lz + 1) * PS + (int64_t)(face == 2 ? 0 : ey + 1) * pitch + lx] = v;
             } else {
-                base[B.off[q] + (face == 4 ? 0 : (int64_t)(ez + 1)) * PS + (int64_t)(ly + 1) * ex + lx] = v;
+                base[B.off[q] + (face == 4 ? 0 : (int64_t)(ez + 1)) * PS + (int64_t)(ly + 1) * pitch + lx] = v;
             }
         }
     }
@@ -572,12 +694,12 @@ __global__ __launch_bounds__(256) void gather_block_kernel(const double *base,
     const BlockDesc &B = blocks[block];
     const int ex = B.ext[0], ey = B.ext[1], ez = B.ext[2];
     const int64_t count = (int64_t)ex * ey * ez;
-    const int64_t PS = (int64_t)(ey + 2) * ex;
+    const int64_t PS = (int64_t)(ey + 2) * B.pitch;
     const double *F = base + B.off[parity];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < count; g += stride) {
         const int64_t x = g % ex, y = (g / ex) % ey, z = g / ((int64_t)ex * ey);
-        dst[g] = F[(z + 1) * PS + (y + 1) * ex + x];
+        dst[g] = F[(z + 1) * PS + (y + 1) * B.pitch + x];
     }
 }
 
@@ -594,13 +716,26 @@ __global__ __launch_bounds__(256) void fill_u32_kernel(unsigned int *p, int64_t 
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
 }
 
-// Streaming copy, 16 bytes per thread per iteration.
-__global__ __launch_bounds__(256) void copy_kernel(uint4 *__restrict__ dst,
-                                                   const uint4 *__restrict__ src, int64_t n16)
+// Streaming copy: each thread moves 4 x 16 bytes per pass (four loads in
+// flight before the stores), grid-stride over the buffer.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void copy_kernel(u32x4 *__restrict__ dst,
+                                                   const u32x4 *__restrict__ src, int64_t n16)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
-        dst[i] = src[i];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        const u32x4 a = __builtin_nontemporal_load(src + i);
+        const u32x4 b = __builtin_nontemporal_load(src + i + stride);
+        const u32x4 c = __builtin_nontemporal_load(src + i + 2 * stride);
+        const u32x4 d = __builtin_nontemporal_load(src + i + 3 * stride);
+        __builtin_nontemporal_store(a, dst + i);
+        __builtin_nontemporal_store(b, dst + i + stride);
+        __builtin_nontemporal_store(c, dst + i + 2 * stride);
+        __builtin_nontemporal_store(d, dst + i + 3 * stride);
+    }
+    for (; i < n16; i += stride) dst[i] = src[i];
 }
 
 int grid_for(int64_t work, int per_block, int cap)
@@ -613,25 +748,37 @@ int grid_for(int64_t work, int per_block, int cap)
 
 constexpr int kMaxGridY = 65535;
 
-// Variant table: (TX, NTY, RY).  Tile = TX x (NTY*RY) cells, TX*NTY threads.
+// Variant table: (TX, NTY, RY, PF).  Tile = TX x (NTY*RY) cells, TX*NTY
+// threads, PF planes of loads in flight ahead of the current one.
 #define J3D_VARIANTS(X) \
-    X(64, 16, 4)        \
-    X(64, 8, 8)         \
-    X(64, 4, 4)         \
-    X(64, 8, 4)         \
-    X(128, 8, 4)        \
-    X(128, 4, 8)        \
-    X(128, 4, 4)        \
-    X(256, 4, 4)        \
-    X(32, 8, 4)         \
-    X(64, 4, 8)
+    X(64, 16, 4, 1)     \
+    X(64, 8, 8, 1)      \
+    X(64, 4, 4, 1)      \
+    X(64, 8, 4, 1)      \
+    X(128, 8, 4, 1)     \
+    X(128, 4, 8, 1)     \
+    X(128, 4, 4, 1)     \
+    X(256, 4, 4, 1)     \
+    X(32, 8, 4, 1)      \
+    X(64, 4, 8, 1)      \
+    X(64, 16, 4, 2)     \
+    X(64, 8, 4, 2)      \
+    X(64, 16, 2, 1)     \
+    X(64, 16, 2, 2)     \
+    X(64, 4, 8, 2)      \
+    X(128, 4, 8, 2)     \
+    X(256, 4, 8, 1)     \
+    X(160, 4, 4, 1)     \
+    X(192, 4, 4, 1)
 
 struct VariantEntry {
-    int tx, nty, ry;
+    int tx, nty, ry, pf;
     void (*fn)(SweepArgs);
+    void (*persistent)(SweepArgs);
 };
 
-#define J3D_ENTRY(TX, NTY, RY) {TX, NTY, RY, sweep_kernel<TX, NTY, RY>},
+#define J3D_ENTRY(TX, NTY, RY, PF) \
+    {TX, NTY, RY, PF, sweep_kernel<TX, NTY, RY, PF>, sweep_kernel_persistent<TX, NTY, RY, PF>},
 const VariantEntry kVariants[] = {J3D_VARIANTS(J3D_ENTRY)};
 #undef J3D_ENTRY
 constexpr int kVariantCount = sizeof(kVariants) / sizeof(kVariants[0]);
@@ -650,7 +797,8 @@ int launch_sweep(int variant, const SweepArgs &a, int grid, void *stream)
 {
     if (variant < 0 || variant >= kVariantCount || grid < 1) return (int)hipErrorInvalidValue;
     const VariantEntry &e = kVariants[variant];
-    hipLaunchKernelGGL(e.fn, dim3(grid), dim3(e.tx * e.nty), 0, (hipStream_t)stream, a);
+    hipLaunchKernelGGL((a.flags & SW_PERSIST) ? e.persistent : e.fn, dim3(grid), dim3(e.tx * e.nty), 0,
+                       (hipStream_t)stream, a);
     return (int)hipGetLastError();
 }
 
@@ -755,8 +903,8 @@ int launch_fill_u32(unsigned int *p, int64_t count, unsigned int value, void *st
 int launch_copy(void *dst, const void *src, uint64_t bytes, void *stream)
 {
     const int64_t n16 = (int64_t)(bytes / 16);
-    hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n16, 256, 256 * 64)), dim3(256), 0,
-                       (hipStream_t)stream, (uint4 *)dst, (const uint4 *)src, n16);
+    hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n16, 4 * 256, 256 * 32)), dim3(256), 0,
+                       (hipStream_t)stream, (u32x4 *)dst, (const u32x4 *)src, n16);
     return (int)hipGetLastError();
 }
 

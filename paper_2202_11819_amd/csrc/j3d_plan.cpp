@@ -223,6 +223,7 @@ j3d_status make_plan(int32_t count, const j3d_problem *probs, bool with_sr, Plan
                     B.org[0] = (int32_t)d.org[0][bx];
                     B.org[1] = (int32_t)d.org[1][by];
                     B.org[2] = (int32_t)d.org[2][bz];
+                    B.pitch = (int32_t)row_pitch(B.ext[0]);
                     B.prob = i;
                     B.nbr[0] = bx > 0 ? index(bx - 1, by, bz) : -1;
                     B.nbr[1] = bx + 1 < d.nb[0] ? index(bx + 1, by, bz) : -1;
@@ -304,6 +305,8 @@ void make_tiles(const Plan &plan, int32_t b0, int32_t b1, int variant, int zchun
 
 void default_tune(const Plan &plan, int cus, j3d_tune *t)
 {
+    // Shapes measured fastest on MI355X for each block width (one workgroup
+    // per tile; the persistent schedule never won for a single problem).
     int exm = 1, eym = 1;
     for (const BlockDesc &B : plan.blocks) {
         exm = std::max(exm, B.ext[0]);
@@ -313,18 +316,22 @@ void default_tune(const Plan &plan, int cus, j3d_tune *t)
     if (exm <= 32)
         v = find_variant(32, 32, 256);
     else if (exm <= 64)
-        v = eym <= 16 ? find_variant(64, 16, 256) : find_variant(64, 64, 1024);
+        v = eym <= 16 ? find_variant(64, 16, 256) : find_variant(64, 32, 256);
     else if (exm <= 128)
-        v = find_variant(128, 32, 1024);
+        v = find_variant(128, 32, 512);
+    else if (exm <= 160)
+        v = find_variant(160, 16, 640);
+    else if (exm <= 192)
+        v = find_variant(192, 16, 768);
     else
         v = find_variant(256, 16, 1024);
     t->variant = v;
     t->blocks_per_cu = 0;
-    // Split z until the launch has a few workgroups per compute unit.
+    // z-chunks of 32 planes, unless the block is shallow or the launch would
+    // then have too few workgroups to fill the chip
     const int ezm = max_ez(plan, 0, (int32_t)plan.blocks.size());
-    int zc = ezm;
-    while (zc > 16 && count_tiles(plan, v, zc) < (uint64_t)(4 * (cus > 0 ? cus : 256)))
-        zc = (zc + 1) / 2;
+    int zc = ezm >= 48 ? 32 : ezm;
+    while (zc > 16 && count_tiles(plan, v, zc) < (uint64_t)(2 * (cus > 0 ? cus : 256))) zc = (zc + 1) / 2;
     t->zchunk = zc >= ezm ? 0 : zc;
 }
 

@@ -314,6 +314,7 @@ j3d_status j3d_pool_admit(j3d_pool *pl, const j3d_problem *p, int64_t max_iters,
         r.n[a] = d.n[a];
     }
     for (int f = 0; f < 6; ++f) r.blk.nbr[f] = -1;
+    r.blk.pitch = (int32_t)row_pitch(d.n[0]);
     r.blk.prob = s;
     r.blk.face_total = 2 * (d.n[1] * d.n[2] + d.n[0] * d.n[2] + d.n[0] * d.n[1]);
     r.iters_done = 0;
