@@ -59,6 +59,18 @@ __device__ __forceinline__ void atomic_max_agent(unsigned long long *p, unsigned
     __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Barrier that orders LDS only.  __syncthreads() is a workgroup release /
+// acquire over all address spaces, which makes every wave wait for its
+// outstanding global loads and stores (including the prefetch of the next
+// plane) before the barrier; the sweep exchanges data between waves through
+// LDS only, so only LDS operations need to complete.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Workgroups of a launch are dispatched round-robin over the XCDs (workgroup
 // i to XCD i % 8).  Give each XCD a contiguous run of tiles so that tiles
 // sharing halo rows run together under one L2.
@@ -121,10 +133,11 @@ struct Shape {
     static constexpr int NT = TX * NTY;   // threads
     static constexpr int LX = TX + 2;     // LDS plane with a one-cell ring
     static constexpr int LY = TY + 2;
-    static constexpr int LDS = 2 * LX * LY;
+    static constexpr int PLANE = LX * LY + 32;  // plane + a sink for masked lanes
+    static constexpr int LDS = 2 * PLANE;
     static_assert(NT >= 2 * TX + 2 * TY, "every halo cell of a plane needs a loader thread");
     static_assert(NT % 64 == 0, "whole waves");
-    static_assert(PF == 1 || PF == 2, "prefetch depth");
+    static_assert(PF >= 1 && PF <= 4, "prefetch depth");
 };
 
 // Uniform description of one tile (lives in scalar registers).
@@ -146,111 +159,113 @@ __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *_
                                                uint64_t hstep, int hl, double *sm)
 {
     using S = Shape<TX, NTY, RY, PF>;
+    // Register ring of NB planes: while plane k is computed from planes
+    // k-1, k, k+1, the loads of planes k+2 .. k+1+PF are in flight.  The loop
+    // is unrolled NB times so every ring index is a compile-time constant and
+    // a load lands in its register without any copy; the slot of plane k-1 is
+    // refilled with plane k+PF+2 right after its last use.
+    constexpr int NB = PF + 3;
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
     const int ex = g.ex;
     const uint32_t rowb = (uint32_t)g.pitch * 8u;
-    // Lanes outside a ragged tile load a clamped (valid) cell and never store.
-    const int cx = FULL ? tx : min(tx, g.nxv - 1);
+    // Lanes outside a ragged tile stay in lock-step with the others (no
+    // divergent branches around the streaming accesses): their buffer offset
+    // lies outside every resource, so their loads return 0 and their stores
+    // are dropped, and their LDS writes go to a sink after the plane.
+    constexpr uint32_t kOutside = 0x80000000u;
     bool vr[RY];
     uint32_t off[RY];  // byte offset of this thread's cell of row r inside a plane
+    int lw[RY];        // LDS slot this thread writes for row r
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         const int ly = ty + NTY * r;
         vr[r] = FULL ? true : (tx < g.nxv && ly < g.nyv);
-        const int cy = FULL ? ly : min(ly, g.nyv - 1);
-        off[r] = (uint32_t)(g.y0 + cy + 1) * rowb + (uint32_t)(g.x0 + cx) * 8u;
+        off[r] = vr[r] ? (uint32_t)(g.y0 + ly + 1) * rowb + (uint32_t)(g.x0 + tx) * 8u : kOutside;
+        lw[r] = vr[r] ? (ly + 1) * S::LX + tx + 1 : S::LX * S::LY + (tid & 31);
     }
     const int x = g.x0 + tx;
     const bool wxm = g.dxm && x == 0, wxp = g.dxp && x == ex - 1;
     const uint32_t xo = (uint32_t)x * 8u;
     const uint64_t psb = g.psb;
+    const int zend = g.z0 + g.nzv;  // last plane read: the z+ neighbour of the last one computed
 
-    double zm[RY], c[RY], zp[RY], zq[RY], zr[RY];
-    {
-        const char *pk = g.cur + (uint64_t)g.z0 * psb;  // plane index z0 = interior plane z0-1
-        const __amdgpu_buffer_rsrc_t r0 = rsrc(pk, psb), r1 = rsrc(pk + psb, psb), r2 = rsrc(pk + 2 * psb, psb);
+    double R[NB][RY];
+    double H[NB];
+    // slot of interior plane z is (z - z0 + 1) mod NB
 #pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            zm[r] = bload<kAuxLoad>(r0, off[r]);
-            c[r] = bload<kAuxLoad>(r1, off[r]);
-            zp[r] = bload<kAuxLoad>(r2, off[r]);
-            zq[r] = zr[r] = 0.0;
-        }
-        if (PF == 2 && g.nzv > 1) {
-            const __amdgpu_buffer_rsrc_t r3 = rsrc(pk + 3 * psb, psb);
+    for (int j = 0; j < NB; ++j) {
+        const int z = g.z0 - 1 + j;
+        H[j] = 0.0;
+        if (z <= zend) {
+            const __amdgpu_buffer_rsrc_t rz = rsrc(g.cur + (uint64_t)(z + 1) * psb, psb);
 #pragma unroll
-            for (int r = 0; r < RY; ++r) zq[r] = bload<kAuxLoad>(r3, off[r]);
+            for (int r = 0; r < RY; ++r) R[j][r] = bload<kAuxLoad>(rz, off[r]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < RY; ++r) R[j][r] = 0.0;
         }
+        if (z >= g.z0 && z < zend) H[j] = hsrc0[(uint64_t)z * hstep];
     }
-    const double *hp = hsrc0 + (uint64_t)g.z0 * hstep;
-    double h = hl >= 0 ? *hp : 0.0;
     double rmax = 0.0;
 
-    for (int kk = 0; kk < g.nzv; ++kk) {
-        const int k = g.z0 + kk;
-        // issue the loads of later planes before this plane's work
-        if (PF == 1) {
-            if (kk + 1 < g.nzv) {
-                const __amdgpu_buffer_rsrc_t rn = rsrc(g.cur + (uint64_t)(k + 3) * psb, psb);
+    for (int kb = 0; kb < g.nzv; kb += NB) {
 #pragma unroll
-                for (int r = 0; r < RY; ++r) zq[r] = bload<kAuxLoad>(rn, off[r]);
-            }
-        } else {
-            if (kk + 2 < g.nzv) {
-                const __amdgpu_buffer_rsrc_t rn = rsrc(g.cur + (uint64_t)(k + 4) * psb, psb);
+        for (int j = 0; j < NB; ++j) {
+            const int kk = kb + j;
+            if (kk < g.nzv) {
+                const int k = g.z0 + kk;
+                const int jm = j, jc = (j + 1) % NB, jp = (j + 2) % NB;
+                double *L = sm + (kk & 1) * S::PLANE;
 #pragma unroll
-                for (int r = 0; r < RY; ++r) zr[r] = bload<kAuxLoad>(rn, off[r]);
-            }
-        }
-        double hn = 0.0;
-        if (hl >= 0 && kk + 1 < g.nzv) hn = hp[(uint64_t)(kk + 1) * hstep];
+                for (int r = 0; r < RY; ++r) L[lw[r]] = R[jc][r];
+                if (hl >= 0) L[hl] = H[jc];
+                lds_barrier();
 
-        double *L = sm + (kk & 1) * (S::LX * S::LY);
+                const __amdgpu_buffer_rsrc_t ro = rsrc(g.nxt + (uint64_t)(k + 1) * psb, psb);
 #pragma unroll
-        for (int r = 0; r < RY; ++r)
-            if (vr[r]) L[(ty + NTY * r + 1) * S::LX + tx + 1] = c[r];
-        if (hl >= 0) L[hl] = h;
-        __syncthreads();
-
-        const __amdgpu_buffer_rsrc_t ro = rsrc(g.nxt + (uint64_t)(k + 1) * psb, psb);
+                for (int r = 0; r < RY; ++r) {
+                    const int li = (ty + NTY * r + 1) * S::LX + tx + 1;
+                    double s = R[jc][r];
+                    s += L[li - 1];
+                    s += L[li + 1];
+                    s += L[li - S::LX];
+                    s += L[li + S::LX];
+                    s += R[jm][r];
+                    s += R[jp][r];
+                    const double v = s * kW;
+                    bstore<kAuxStore>(ro, off[r], v);
+                    if (g.fused && vr[r]) {
+                        // this block's new face values, straight into the
+                        // neighbours' halo storage of the next iterate
+                        const int y = g.y0 + ty + NTY * r;
+                        if (wxm) st_cell(g.dxm + ((uint64_t)k * g.ey + y) * 8u, v);
+                        if (wxp) st_cell(g.dxp + ((uint64_t)k * g.ey + y) * 8u, v);
+                        if (g.dym && y == 0) st_cell(g.dym + (uint64_t)(k + 1) * g.psym + xo, v);
+                        if (g.dyp && y == g.ey - 1) st_cell(g.dyp + (uint64_t)(k + 1) * g.psyp + xo, v);
+                        if (g.dzm && k == 0) st_cell(g.dzm + off[r], v);
+                        if (g.dzp && k == g.ez - 1) st_cell(g.dzp + off[r], v);
+                    }
+                    if (g.want_res) {
+                        const double d = vr[r] ? fabs(v - R[jc][r]) : 0.0;
+                        rmax = d > rmax ? d : rmax;
+                    }
+                }
+                // refill the slot of plane k-1 with plane k-1+NB; past the
+                // tile's last plane the resource is empty (loads return 0),
+                // so the loads issue unconditionally and the wait counts stay
+                // exact
+                const int zn = k - 1 + NB;
+                {
+                    const bool live = zn <= zend;
+                    const __amdgpu_buffer_rsrc_t rn =
+                        rsrc(g.cur + (uint64_t)((live ? zn : zend) + 1) * psb, live ? psb : 0);
 #pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            if (!vr[r]) continue;
-            const int li = (ty + NTY * r + 1) * S::LX + tx + 1;
-            double s = c[r];
-            s += L[li - 1];
-            s += L[li + 1];
-            s += L[li - S::LX];
-            s += L[li + S::LX];
-            s += zm[r];
-            s += zp[r];
-            const double v = s * kW;
-            bstore<kAuxStore>(ro, off[r], v);
-            if (g.fused) {
-                // this block's new face values, straight into the neighbours'
-                // halo storage of the next iterate (rare lanes / planes)
-                const int y = g.y0 + ty + NTY * r;
-                if (wxm) st_cell(g.dxm + ((uint64_t)k * g.ey + y) * 8u, v);
-                if (wxp) st_cell(g.dxp + ((uint64_t)k * g.ey + y) * 8u, v);
-                if (g.dym && y == 0) st_cell(g.dym + (uint64_t)(k + 1) * g.psym + xo, v);
-                if (g.dyp && y == g.ey - 1) st_cell(g.dyp + (uint64_t)(k + 1) * g.psyp + xo, v);
-                if (g.dzm && k == 0) st_cell(g.dzm + off[r], v);
-                if (g.dzp && k == g.ez - 1) st_cell(g.dzp + off[r], v);
-            }
-            if (g.want_res) {
-                const double d = fabs(v - c[r]);
-                rmax = d > rmax ? d : rmax;
+                    for (int r = 0; r < RY; ++r) R[jm][r] = bload<kAuxLoad>(rn, off[r]);
+                    H[jm] = hsrc0[(uint64_t)(zn < zend ? zn : zend - 1) * hstep];
+                }
             }
         }
-#pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            zm[r] = c[r];
-            c[r] = zp[r];
-            zp[r] = zq[r];
-            if (PF == 2) zq[r] = zr[r];
-        }
-        h = hn;
     }
     return rmax;
 }
@@ -285,15 +300,16 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
     char *base = reinterpret_cast<char *>(a.base);
     g.cur = base + B->off[p] * 8;
     g.nxt = base + B->off[p ^ 1] * 8;
-    // Balanced tiling: a block axis of e cells is cut into n = ceil(e / T)
-    // tiles of near-equal length (each <= T), so no tile is a thin remainder.
+    // x tiles start on multiples of TX (rows stay cache-line aligned); y and
+    // z are cut into n = ceil(e / T) near-equal pieces (each <= T), so no
+    // tile is a thin remainder along them.
     {
-        const int ntx = (ex + TX - 1) / TX, nty = (ey + S::TY - 1) / S::TY;
+        const int nty = (ey + S::TY - 1) / S::TY;
         const int ntz = (ez + a.zchunk - 1) / a.zchunk;
-        g.x0 = (int)((int64_t)tl.tx * ex / ntx);
+        g.x0 = tl.tx * TX;
+        g.nxv = min(TX, ex - g.x0);
         g.y0 = (int)((int64_t)tl.ty * ey / nty);
         g.z0 = (int)((int64_t)tl.tz * ez / ntz);
-        g.nxv = (int)((int64_t)(tl.tx + 1) * ex / ntx) - g.x0;
         g.nyv = (int)((int64_t)(tl.ty + 1) * ey / nty) - g.y0;
         g.nzv = (int)((int64_t)(tl.tz + 1) * ez / ntz) - g.z0;
     }
@@ -325,7 +341,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
     // points at plane index 0's value; plane k adds k*hstep doubles.
     const int tid = threadIdx.x;
     int hl = -1;
-    const double *hsrc0 = a.base;
+    const double *hsrc0 = a.base + B->off[p];  // lanes without a halo role read a valid cell
     uint64_t hstep = 0;
     const uint64_t ps = (uint64_t)(ey + 2) * pitch;
     const double *curd = a.base + B->off[p];
@@ -716,26 +732,28 @@ __global__ __launch_bounds__(256) void fill_u32_kernel(unsigned int *p, int64_t 
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
 }
 
-// Streaming copy: each thread moves 4 x 16 bytes per pass (four loads in
-// flight before the stores), grid-stride over the buffer.
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+// Streaming copy: each workgroup moves one 16 KiB chunk in a single pass
+// (four 16-byte loads per thread in flight, then four stores), the fastest
+// shape measured for a 1:1 read/write stream on MI355X.  The last chunk's
+// resource is clipped to the buffer, so the tail needs no branch.
+constexpr int kCopyChunk = 16384;
 
-__global__ __launch_bounds__(256) void copy_kernel(u32x4 *__restrict__ dst,
-                                                   const u32x4 *__restrict__ src, int64_t n16)
+__global__ __launch_bounds__(256) void copy_kernel(char *__restrict__ dst, const char *__restrict__ src,
+                                                   uint64_t bytes)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < n16; i += 4 * stride) {
-        const u32x4 a = __builtin_nontemporal_load(src + i);
-        const u32x4 b = __builtin_nontemporal_load(src + i + stride);
-        const u32x4 c = __builtin_nontemporal_load(src + i + 2 * stride);
-        const u32x4 d = __builtin_nontemporal_load(src + i + 3 * stride);
-        __builtin_nontemporal_store(a, dst + i);
-        __builtin_nontemporal_store(b, dst + i + stride);
-        __builtin_nontemporal_store(c, dst + i + 2 * stride);
-        __builtin_nontemporal_store(d, dst + i + 3 * stride);
-    }
-    for (; i < n16; i += stride) dst[i] = src[i];
+    const uint64_t base = (uint64_t)blockIdx.x * kCopyChunk;
+    const uint64_t left = bytes - base;
+    const int len = (int)(left < (uint64_t)kCopyChunk ? left : (uint64_t)kCopyChunk);
+    const __amdgpu_buffer_rsrc_t rs = rsrc(src + base, (uint64_t)len);
+    const __amdgpu_buffer_rsrc_t rd = rsrc(dst + base, (uint64_t)len);
+    typedef int i32x4 __attribute__((ext_vector_type(4)));
+    i32x4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        v[u] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)((threadIdx.x + u * 256) * 16), 0, kAuxNT);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        __builtin_amdgcn_raw_buffer_store_b128(v[u], rd, (int)((threadIdx.x + u * 256) * 16), 0, kAuxNT);
 }
 
 int grid_for(int64_t work, int per_block, int cap)
@@ -749,7 +767,7 @@ int grid_for(int64_t work, int per_block, int cap)
 constexpr int kMaxGridY = 65535;
 
 // Variant table: (TX, NTY, RY, PF).  Tile = TX x (NTY*RY) cells, TX*NTY
-// threads, PF planes of loads in flight ahead of the current one.
+// threads, loads of PF planes beyond the next one in flight.
 #define J3D_VARIANTS(X) \
     X(64, 16, 4, 1)     \
     X(64, 8, 8, 1)      \
@@ -767,9 +785,15 @@ constexpr int kMaxGridY = 65535;
     X(64, 16, 2, 2)     \
     X(64, 4, 8, 2)      \
     X(128, 4, 8, 2)     \
-    X(256, 4, 8, 1)     \
+    X(256, 4, 4, 2)     \
     X(160, 4, 4, 1)     \
-    X(192, 4, 4, 1)
+    X(192, 4, 4, 1)     \
+    X(64, 4, 8, 3)      \
+    X(64, 4, 4, 2)      \
+    X(64, 4, 4, 4)      \
+    X(64, 8, 4, 3)      \
+    X(128, 4, 8, 3)     \
+    X(128, 4, 4, 4)
 
 struct VariantEntry {
     int tx, nty, ry, pf;
@@ -902,9 +926,11 @@ int launch_fill_u32(unsigned int *p, int64_t count, unsigned int value, void *st
 
 int launch_copy(void *dst, const void *src, uint64_t bytes, void *stream)
 {
-    const int64_t n16 = (int64_t)(bytes / 16);
-    hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n16, 4 * 256, 256 * 32)), dim3(256), 0,
-                       (hipStream_t)stream, (u32x4 *)dst, (const u32x4 *)src, n16);
+    const uint64_t chunks = (bytes + kCopyChunk - 1) / kCopyChunk;
+    if (chunks == 0) return 0;
+    if (chunks > 0x7fffffffull) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)chunks), dim3(256), 0, (hipStream_t)stream, (char *)dst,
+                       (const char *)src, bytes);
     return (int)hipGetLastError();
 }
 

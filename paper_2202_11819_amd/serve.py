@@ -1,0 +1,208 @@
+"""Request loop for the served form, its serial baseline, and their benchmarks.
+
+Serving here is continuous batching: requests that arrive while others run
+are admitted as soon as a slot and enough of the HBM budget are free, their
+grids stay resident, and every round advances all running requests together
+(one fused launch per sweep over all of their tiles).  Finished requests are
+copied to page-locked host memory while later rounds run.  Latency is
+measured from a request's arrival to its result being in host memory.
+
+The baseline serves the same arrival trace one request at a time in arrival
+order with the plain solver (a solver per request, graph mode); its latencies
+follow from the measured service times: finish_i = max(arrival_i,
+finish_{i-1}) + service_i.
+"""
+from __future__ import annotations
+
+import collections
+import json
+import math
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import j3d
+from . import workloads as W
+from .api import Batch, Pool, Solver
+
+
+def nearest_rank(values, q):
+    """Nearest-rank percentile (q in (0, 100])."""
+    v = sorted(values)
+    if not v:
+        return float("nan")
+    k = max(1, math.ceil(q / 100.0 * len(v)))
+    return v[k - 1]
+
+
+def serve_pool(trace, budget_bytes, max_slots=256, round_sweeps=50, check_every=50, tol=0.0,
+               keep_results=False, log=None):
+    """Serve `trace` (list of workloads.Request) in real time; per-request records."""
+    pool = Pool(budget_bytes, max_slots=max_slots)
+    problems = [W.to_problem(r.spec) for r in trace]
+    pending = collections.deque(range(len(trace)))
+    waiting = collections.deque()
+    active = {}
+    recs = [None] * len(trace)
+    done = 0
+    busy = False
+    t0 = time.perf_counter()
+    rounds = 0
+    try:
+        while done < len(trace):
+            now = time.perf_counter() - t0
+            while pending and trace[pending[0]].arrival <= now:
+                waiting.append(pending.popleft())
+            finished, busy = pool.poll()
+            now = time.perf_counter() - t0
+            for slot in finished:
+                i = active.pop(slot)
+                u, res, it = pool.result(slot)
+                recs[i] = {"i": i, "arrival": trace[i].arrival, "done": now, "latency": now - trace[i].arrival,
+                           "residual": res, "iters": it, "cells": problems[i].cells}
+                if keep_results:
+                    recs[i]["u"] = u.copy()
+                pool.release(slot)
+                done += 1
+                if log and done % 100 == 0:
+                    log(f"[serve] {done}/{len(trace)} done at {now:.1f} s, {len(active)} running")
+            while waiting:
+                i = waiting[0]
+                slot = pool.try_admit(problems[i], trace[i].spec.iters, tol=tol, check_every=check_every)
+                if slot is None:
+                    if not active and not busy:
+                        raise RuntimeError(f"request {i} ({problems[i].n}) does not fit an empty pool")
+                    break
+                waiting.popleft()
+                active[slot] = i
+            if not busy and active:
+                pool.step(round_sweeps)
+                rounds += 1
+                busy = True
+            elif not active and not waiting and pending:
+                # idle until the next arrival
+                gap = trace[pending[0]].arrival - (time.perf_counter() - t0)
+                if gap > 0:
+                    time.sleep(min(gap, 0.001))
+    finally:
+        pool.close()
+    return recs, rounds
+
+
+def serve_serial(trace, log=None, keep_results=False):
+    """The same trace, one plain solve at a time in arrival order."""
+    recs = []
+    finish = 0.0
+    for i, r in enumerate(trace):
+        t0 = time.perf_counter()
+        s = Solver(r.spec.n, nblk=r.spec.nblk, bc=r.spec.bc, seed=r.spec.seed, pid=r.spec.pid)
+        res = s.run(r.spec.iters, mode="graph", residual=True)
+        u = s.get_interior()
+        s.close()
+        service = time.perf_counter() - t0
+        start = max(r.arrival, finish)
+        finish = start + service
+        rec = {"i": i, "arrival": r.arrival, "done": finish, "latency": finish - r.arrival, "service": service,
+               "residual": res, "iters": r.spec.iters, "cells": int(np.prod(r.spec.n))}
+        if keep_results:
+            rec["u"] = u
+        recs.append(rec)
+        if log and (i + 1) % 100 == 0:
+            log(f"[serial] {i + 1}/{len(trace)}")
+    return recs
+
+
+def summarize(recs, warmup):
+    m = [r for r in recs if r["i"] >= warmup]
+    lat = [r["latency"] for r in m]
+    span = max(r["done"] for r in m) - min(r["arrival"] for r in m)
+    lups = sum(r["cells"] * r["iters"] for r in m)
+    return {"solves_per_s": round(len(m) / span, 3), "p50_ms": round(1e3 * nearest_rank(lat, 50), 2),
+            "p99_ms": round(1e3 * nearest_rank(lat, 99), 2), "mean_ms": round(1e3 * float(np.mean(lat)), 2),
+            "GLUPs": round(lups / span / 1e9, 2), "requests": len(m), "span_s": round(span, 2)}
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bench_serve(args):
+    """Served workload: Poisson arrivals at 0.8 x the serial capacity."""
+    count = int(getattr(args, "requests", 0) or 1100)
+    warmup = min(100, count // 10)
+    base = W.serve_trace(count=count, rate=1.0)
+    # serial capacity from a sample of the same request mix
+    sample = base[: min(40, count)]
+    t0 = time.perf_counter()
+    serve_serial(W.rescale_arrivals(sample, 1e9))
+    mean_service = (time.perf_counter() - t0) / len(sample)
+    rate = 0.8 / mean_service
+    trace = W.rescale_arrivals(base, rate)
+    _log(f"[serve] mean serial service {mean_service * 1e3:.1f} ms -> arrival rate {rate:.2f}/s")
+    free = torch.cuda.mem_get_info()[0]
+    budget = int(min(200e9, 0.85 * free))
+    recs, rounds = serve_pool(trace, budget, log=_log)
+    pool_sum = summarize(recs, warmup)
+    srecs = serve_serial(trace, log=_log)
+    serial_sum = summarize(srecs, warmup)
+    out = {"metric": "served solves/s and p50/p99 latency (arrival to result on host)",
+           "value": pool_sum["solves_per_s"], "unit": "solves/s", "higher_is_better": True,
+           "pool": pool_sum, "serial_plain": serial_sum, "rounds": rounds,
+           "config": {"workload": f"{count} Jacobi3D solve requests, Poisson arrivals at {rate:.2f}/s "
+                                  f"(0.8 x serial capacity), per-axis size U{{32..384}}, 50..2000 sweeps, "
+                                  f"residual every 50, tol 0, budget {budget / 1e9:.0f} GB, "
+                                  f"first {warmup} discarded", "dtype": "f64"}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """Batched workload: 256 problems in one launch per sweep vs a per-problem loop."""
+    from .autotune import tune_batch
+
+    specs = W.batch()
+    problems = [W.to_problem(s) for s in specs]
+    iters = [s.iters for s in specs]
+    lups = sum(p.cells * it for p, it in zip(problems, iters))
+    tune = tune_batch(problems, iters, log=_log, force=getattr(args, "retune", False))
+    _log(f"[batch] tune {tune} ({j3d.variants()[tune[0]]})")
+
+    def timed_batch(t):
+        b = Batch(problems, iters, tune=t)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.run(residuals=False)
+        e1.record()
+        e1.synchronize()
+        b.close()
+        return e0.elapsed_time(e1) * 1e-3
+
+    timed_batch(tune)
+    tb = min(timed_batch(tune) for _ in range(2))
+    tdef = timed_batch(None)
+    # per-problem loop: each problem solved on its own with the plain solver
+    run_s = 0.0
+    wall0 = time.perf_counter()
+    for s in specs:
+        sol = Solver(s.n, bc=s.bc, seed=s.seed, pid=s.pid)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sol.run(s.iters, mode="graph")
+        e1.record()
+        e1.synchronize()
+        run_s += e0.elapsed_time(e1) * 1e-3
+        sol.close()
+    wall = time.perf_counter() - wall0
+    out = {"metric": "batched FP64 Jacobi3D GLUP/s (256 problems, one launch per sweep)",
+           "value": round(lups / tb / 1e9, 2), "unit": "GLUP/s", "higher_is_better": True,
+           "batched_s": round(tb, 4), "batched_default_tune_s": round(tdef, 4),
+           "per_problem_loop_s": round(run_s, 4), "per_problem_loop_GLUPs": round(lups / run_s / 1e9, 2),
+           "per_problem_loop_wall_s": round(wall, 2), "speedup_vs_loop": round(run_s / tb, 3),
+           "tune": list(tune), "tile": list(j3d.variants()[tune[0]]),
+           "config": {"workload": f"256 independent problems, per-axis size log-uniform in [32, 256], "
+                                  f"per-face bc U[-1,1], 100..1000 sweeps, {lups / 1e9:.1f} GLUP in total",
+                      "dtype": "f64"}}
+    print(json.dumps(out), flush=True)

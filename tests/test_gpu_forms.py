@@ -1,0 +1,194 @@
+"""GPU parity of the batched and served forms (through the C ABI).
+
+Every problem of a batch and every request of the pool must reproduce the
+oracle's bits and residual exactly, whatever the tile shape or schedule, and
+a request must give the same bits alone and in a mix.
+"""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+NTH = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import oracle
+    from paper_2202_11819_amd import api, j3d
+    from paper_2202_11819_amd import workloads as W
+    oracle.lib()
+    return oracle, api, j3d, W
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _mix(W, count=14, seed=3):
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(count):
+        n = tuple(int(v) for v in rng.integers(5, 90, 3))
+        bc = tuple(float(v) for v in rng.uniform(-1, 1, 6))
+        it = int(rng.integers(0, 30)) if i % 5 else (0 if i == 0 else 1)
+        nblk = (1, 1, 1)
+        split = None
+        if i % 4 == 3 and min(n) >= 4:
+            nblk = (2, 1, 2)
+            split = ([n[0] // 2, n[0] - n[0] // 2], None, [1, n[2] - 1])
+        specs.append(W.Spec(n=n, nblk=nblk, split=split, bc=bc, seed=9, pid=i, iters=it))
+    return specs
+
+
+def _problem(api, s):
+    from paper_2202_11819_amd import j3d
+    return j3d.Problem(s.n, s.nblk, s.split, s.bc, s.seed, s.pid)
+
+
+@pytest.mark.parametrize("tune", [None, (0, 0, 0), (9, 16, 2), (8, 8, 3), (5, 0, 1)])
+def test_batch_matches_oracle(env, tune):
+    oracle, api, j3d, W = env
+    specs = _mix(W)
+    say(f"batch of {len(specs)} with tune {tune}")
+    with api.Batch([_problem(api, s) for s in specs], [s.iters for s in specs], tune=tune) as b:
+        res = b.run()
+        for i, s in enumerate(specs):
+            want, want_r, _ = oracle.jacobi(s.n, s.iters, bc=s.bc, seed=s.seed, pid=s.pid, nthreads=NTH)
+            assert np.array_equal(b.get_interior(i), want), (i, s.n, s.iters)
+            assert res[i] == want_r, i
+
+
+def test_batch_run_twice_is_refused(env):
+    _, api, j3d, W = env
+    specs = _mix(W, count=3)
+    with api.Batch([_problem(api, s) for s in specs], [s.iters for s in specs]) as b:
+        b.run()
+        with pytest.raises(j3d.J3DError) as e:
+            b.run()
+        assert e.value.status == j3d.J3D_ESTATE
+
+
+def test_batch_every_autotune_candidate_is_identical(env):
+    _, api, j3d, W = env
+    from paper_2202_11819_amd import autotune
+    specs = _mix(W, count=6, seed=11)
+    probs = [_problem(api, s) for s in specs]
+    iters = [s.iters for s in specs]
+    ref = None
+    for cand in autotune.candidates(probs)[::5]:
+        with api.Batch(probs, iters, tune=cand) as b:
+            res = b.run()
+            outs = [b.get_interior(i) for i in range(len(specs))]
+        if ref is None:
+            ref = (outs, res)
+        else:
+            assert all(np.array_equal(a, c) for a, c in zip(outs, ref[0])), cand
+            assert np.array_equal(res, ref[1]), cand
+
+
+def _requests(W, count=12, seed=4, spread=0.02):
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    for i in range(count):
+        t += float(rng.exponential(spread))
+        n = tuple(int(v) for v in rng.integers(8, 100, 3))
+        it = int(rng.integers(1, 160))
+        out.append(W.Request(arrival=t, spec=W.Spec(n=n, seed=5, pid=i, iters=it)))
+    return out
+
+
+def test_pool_requests_match_oracle_and_solo_runs(env):
+    oracle, api, j3d, W = env
+    from paper_2202_11819_amd import serve
+    trace = _requests(W)
+    recs, rounds = serve.serve_pool(trace, budget_bytes=2 << 30, max_slots=8, round_sweeps=50,
+                                    check_every=50, keep_results=True)
+    assert rounds > 1
+    for r, req in zip(recs, trace):
+        s = req.spec
+        want, want_r, done = oracle.jacobi(s.n, s.iters, seed=s.seed, pid=s.pid, check_every=50, nthreads=NTH)
+        assert r["iters"] == done == s.iters
+        assert np.array_equal(r["u"], want), r["i"]
+        assert r["residual"] == want_r, r["i"]
+    # alone in a pool of its own: the same bits
+    for req in trace[:4]:
+        alone, _ = serve.serve_pool([W.Request(arrival=0.0, spec=req.spec)], budget_bytes=1 << 30,
+                                    max_slots=1, keep_results=True)
+        mixed = recs[trace.index(req)]
+        assert np.array_equal(alone[0]["u"], mixed["u"]) and alone[0]["residual"] == mixed["residual"]
+
+
+def test_pool_early_exit_matches_checked_oracle(env):
+    oracle, api, j3d, W = env
+    n = (30, 26, 22)
+    # tolerance reached after some check point
+    _, r40, _ = oracle.jacobi(n, 40, seed=6)
+    tol = r40
+    want, want_r, done = oracle.jacobi(n, 500, seed=6, tol=tol, check_every=10)
+    assert done < 500
+    with api.Pool(1 << 30, max_slots=4) as pool:
+        slot = pool.try_admit(j3d.Problem(n, seed=6), 500, tol=tol, check_every=10)
+        finished = []
+        while not finished:
+            got, busy = pool.poll()
+            finished += got
+            if not busy and not finished:
+                pool.step(7)  # rounds that do not line up with the check points
+        u, r, it = pool.result(slot)
+        assert it == done and r == want_r
+        assert np.array_equal(u, want)
+        pool.release(slot)
+
+
+def test_pool_admission_limits_and_errors(env):
+    _, api, j3d, W = env
+    small = j3d.Problem((32, 32, 32))
+    need = j3d.j3d_pool_request_bytes(small)
+    with api.Pool(2 * need + need // 2, max_slots=3) as pool:
+        a = pool.try_admit(small, 10)
+        b = pool.try_admit(small, 10)
+        assert a is not None and b is not None
+        assert pool.try_admit(small, 10) is None          # budget exhausted
+        used, nbytes = pool.usage()
+        assert used == 2 and nbytes == 2 * need
+        pool.release(a)
+        c = pool.try_admit(small, 10)                      # freed bytes are reused
+        assert c is not None
+        with pytest.raises(j3d.J3DError) as e:
+            j3d.j3d_pool_result(pool.h, b)                  # not finished yet
+        assert e.value.status == j3d.J3D_ESTATE
+        pool.release(b)
+        pool.release(c)
+        with pytest.raises(j3d.J3DError) as e:
+            pool.release(c)                                # double release
+        assert e.value.status == j3d.J3D_ESTATE
+        with pytest.raises(j3d.J3DError) as e:
+            j3d.j3d_pool_admit(pool.h, j3d.Problem((64, 64, 64), (2, 1, 1)), 5, 0.0, 0, 1 << 20)
+        assert e.value.status == j3d.J3D_EINVAL
+    with api.Pool(1 << 28, max_slots=1) as pool:
+        assert pool.try_admit(small, 5) is not None
+        st, _ = j3d.j3d_pool_try_admit(pool.h, small, 5, 0.0, 0, pool.results[0][0].data_ptr())
+        assert st == j3d.J3D_EBUSY
+
+
+def test_pool_zero_iterations_returns_initial_grid(env):
+    oracle, api, j3d, W = env
+    with api.Pool(1 << 28, max_slots=2) as pool:
+        slot = pool.try_admit(j3d.Problem((17, 9, 5), seed=3, pid=2), 0)
+        import time
+        got = []
+        t0 = time.time()
+        while not got and time.time() - t0 < 20:
+            g, busy = pool.poll()
+            got += g
+        assert got == [slot]
+        u, r, it = pool.result(slot)
+        assert it == 0 and r == 0.0
+        assert np.array_equal(u, oracle.init_interior((17, 9, 5), 3, 2))
