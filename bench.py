@@ -267,6 +267,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--requests", type=int, default=1100, help="serve workload: number of requests")
+    ap.add_argument("--serve-dump", default="", help="serve workload: write per-request records here")
+    ap.add_argument("--retune", action="store_true", help="batch workload: ignore the tuning cache")
+    ap.add_argument("--load", type=float, default=0.8, help="serve workload: arrival rate / serial capacity")
+    ap.add_argument("--fill-cells", type=int, default=-1, help="serve workload: pool round policy (-1: default)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "

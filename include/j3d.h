@@ -236,10 +236,19 @@ j3d_status j3d_pool_create(void *dev_arena, uint64_t arena_bytes, uint64_t budge
 j3d_status j3d_pool_admit(j3d_pool *pl, const j3d_problem *p, int64_t max_iters, double tol,
                           int32_t check_every, double *host_result, int32_t *slot);
 
-/* Enqueue one round of up to `sweeps` sweeps for every running request (each
- * request stops at its own limit).  Asynchronous.  ESTATE if a round is still
- * in flight (poll first).                                                   */
+/* Enqueue one round of up to `sweeps` sweeps for the running requests the
+ * round policy picks (each request stops at its own limit and never passes a
+ * residual check point within a round).  Asynchronous.  ESTATE if a round is
+ * still in flight (poll first).                                             */
 j3d_status j3d_pool_step(j3d_pool *pl, int32_t sweeps);
+
+/* Round policy.  fill_cells > 0: requests join a round in order of least
+ * remaining work (cells x sweeps left) until the round holds at least
+ * fill_cells cells; a request left out of max_wait_rounds consecutive rounds
+ * joins first.  fill_cells == 0: every running request joins every round.
+ * Default: fill_cells = 2^25, max_wait_rounds = 32.  Results do not depend on
+ * the policy, only latencies do.                                            */
+j3d_status j3d_pool_set_policy(j3d_pool *pl, int64_t fill_cells, int32_t max_wait_rounds);
 
 /* Non-blocking progress: retires a completed round (updating every request's
  * sweep count and residual, deciding which finished), starts the result

@@ -136,6 +136,9 @@ class Pool:
     def step(self, sweeps=50):
         C.j3d_pool_step(self.h, sweeps)
 
+    def set_policy(self, fill_cells, max_wait_rounds=32):
+        C.j3d_pool_set_policy(self.h, fill_cells, max_wait_rounds)
+
     def poll(self):
         return C.j3d_pool_poll(self.h, self.max_slots)
 

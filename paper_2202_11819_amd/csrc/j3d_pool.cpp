@@ -22,8 +22,10 @@ using namespace j3d;
 
 namespace {
 
-constexpr int kPoolVariantTileX = 64, kPoolVariantTileY = 64, kPoolVariantThreads = 1024;
-constexpr int kPoolZchunk = 64;
+// 64x32 tiles of 256 threads and 32-plane z-chunks: enough workgroups per
+// request that a round of a few mid-sized requests fills the GPU
+constexpr int kPoolVariantTileX = 64, kPoolVariantTileY = 32, kPoolVariantThreads = 256;
+constexpr int kPoolZchunk = 32;
 constexpr int64_t kPoolTilesPerReq = 4096;
 
 enum ReqState { R_FREE = 0, R_RUNNING, R_COPYING, R_DONE, R_REPORTED };
@@ -37,6 +39,7 @@ struct Req {
     int64_t iters_done = 0, max_iters = 0;
     double tol = 0.0, residual = 0.0;
     int32_t check_every = 0;
+    int32_t waited = 0;  // consecutive rounds this request was left out of
     double *host_result = nullptr;
     hipEvent_t gather_ev = nullptr, copy_ev = nullptr;
 };
@@ -114,6 +117,11 @@ struct j3d_pool {
     Tile *host_tiles = nullptr;
     BlockDesc *host_blocks = nullptr;
     std::vector<int32_t> ready;
+    // round policy: shortest remaining work first until the round holds at
+    // least fill_cells cells (0: every running request joins every round);
+    // a request left out of max_wait consecutive rounds joins first
+    int64_t fill_cells = int64_t(1) << 25;
+    int32_t max_wait = 32;
 };
 
 namespace {
@@ -322,6 +330,7 @@ j3d_status j3d_pool_admit(j3d_pool *pl, const j3d_problem *p, int64_t max_iters,
     r.tol = tol;
     r.check_every = check_every;
     r.residual = 0.0;
+    r.waited = 0;
     r.host_result = host_result;
     pl->host_blocks[s] = r.blk;
     BlockDesc *dblk = reinterpret_cast<BlockDesc *>(pl->arena + pl->lay.off_blocks);
@@ -354,9 +363,39 @@ j3d_status j3d_pool_step(j3d_pool *pl, int32_t sweeps)
     if (pl->round_busy) return set_error(J3D_ESTATE, "a round is still in flight");
     pl->round.clear();
     std::vector<Tile> tiles;
+    // choose this round's requests
+    struct Cand {
+        bool starving;
+        double remaining;  // cell-sweeps left
+        int32_t slot;
+    };
+    std::vector<Cand> cands;
+    for (int32_t s = 0; s < pl->max_slots; ++s) {
+        const Req &r = pl->reqs[s];
+        if (r.state != R_RUNNING) continue;
+        cands.push_back(Cand{r.waited >= pl->max_wait,
+                             (double)(r.max_iters - r.iters_done) * (double)(r.n[0] * r.n[1] * r.n[2]), s});
+    }
+    std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) {
+        if (a.starving != b.starving) return a.starving;
+        if (a.remaining != b.remaining) return a.remaining < b.remaining;
+        return a.slot < b.slot;
+    });
+    std::vector<char> chosen(pl->max_slots, 0);
+    int64_t cells = 0;
+    for (const Cand &c : cands) {
+        if (pl->fill_cells > 0 && cells >= pl->fill_cells) break;
+        chosen[c.slot] = 1;
+        const Req &r = pl->reqs[c.slot];
+        cells += r.n[0] * r.n[1] * r.n[2];
+    }
+    for (const Cand &c : cands) {
+        Req &r = pl->reqs[c.slot];
+        r.waited = chosen[c.slot] ? 0 : r.waited + 1;
+    }
     for (int32_t s = 0; s < pl->max_slots; ++s) {
         Req &r = pl->reqs[s];
-        if (r.state != R_RUNNING) continue;
+        if (r.state != R_RUNNING || !chosen[s]) continue;
         const int64_t base = r.iters_done;
         int64_t limit = r.max_iters;
         if (r.check_every > 0) limit = std::min(limit, (base / r.check_every + 1) * r.check_every);
@@ -462,6 +501,17 @@ j3d_status j3d_pool_result(j3d_pool *pl, int32_t slot, double *residual, int64_t
     if (r.state != R_DONE && r.state != R_REPORTED) return set_error(J3D_ESTATE, "slot %d has no result", slot);
     if (residual) *residual = r.residual;
     if (iters_done) *iters_done = r.iters_done;
+    return J3D_OK;
+}
+
+j3d_status j3d_pool_set_policy(j3d_pool *pl, int64_t fill_cells, int32_t max_wait_rounds)
+{
+    if (!pl) return set_error(J3D_EINVAL, "pool is NULL");
+    if (fill_cells < 0 || max_wait_rounds < 1)
+        return set_error(J3D_EINVAL, "fill_cells %lld < 0 or max_wait_rounds %d < 1", (long long)fill_cells,
+                         max_wait_rounds);
+    pl->fill_cells = fill_cells;
+    pl->max_wait = max_wait_rounds;
     return J3D_OK;
 }
 

@@ -38,9 +38,12 @@ def nearest_rank(values, q):
 
 
 def serve_pool(trace, budget_bytes, max_slots=256, round_sweeps=50, check_every=50, tol=0.0,
-               keep_results=False, log=None):
-    """Serve `trace` (list of workloads.Request) in real time; per-request records."""
+               keep_results=False, log=None, fill_cells=None):
+    """Serve `trace` (list of workloads.Request) in real time; per-request records.
+    fill_cells: round policy (None keeps the library default)."""
     pool = Pool(budget_bytes, max_slots=max_slots)
+    if fill_cells is not None:
+        pool.set_policy(fill_cells)
     problems = [W.to_problem(r.spec) for r in trace]
     pending = collections.deque(range(len(trace)))
     waiting = collections.deque()
@@ -129,7 +132,7 @@ def _log(*a):
 
 
 def bench_serve(args):
-    """Served workload: Poisson arrivals at 0.8 x the serial capacity."""
+    """Served workload: Poisson arrivals at `load` (default 0.8) x the serial capacity."""
     count = int(getattr(args, "requests", 0) or 1100)
     warmup = min(100, count // 10)
     base = W.serve_trace(count=count, rate=1.0)
@@ -138,20 +141,27 @@ def bench_serve(args):
     t0 = time.perf_counter()
     serve_serial(W.rescale_arrivals(sample, 1e9))
     mean_service = (time.perf_counter() - t0) / len(sample)
-    rate = 0.8 / mean_service
+    load = float(getattr(args, "load", 0.8) or 0.8)
+    rate = load / mean_service
     trace = W.rescale_arrivals(base, rate)
-    _log(f"[serve] mean serial service {mean_service * 1e3:.1f} ms -> arrival rate {rate:.2f}/s")
+    _log(f"[serve] mean serial service {mean_service * 1e3:.1f} ms -> arrival rate {rate:.2f}/s ({load} x capacity)")
     free = torch.cuda.mem_get_info()[0]
     budget = int(min(200e9, 0.85 * free))
-    recs, rounds = serve_pool(trace, budget, log=_log)
+    fill = int(getattr(args, "fill_cells", -1))
+    recs, rounds = serve_pool(trace, budget, log=_log, fill_cells=None if fill < 0 else fill)
     pool_sum = summarize(recs, warmup)
     srecs = serve_serial(trace, log=_log)
     serial_sum = summarize(srecs, warmup)
+    dump = getattr(args, "serve_dump", "")
+    if dump:
+        with open(dump, "w") as f:
+            json.dump({"rate": rate, "pool": recs, "serial": srecs,
+                       "specs": [[list(r.spec.n), r.spec.iters] for r in trace]}, f)
     out = {"metric": "served solves/s and p50/p99 latency (arrival to result on host)",
            "value": pool_sum["solves_per_s"], "unit": "solves/s", "higher_is_better": True,
-           "pool": pool_sum, "serial_plain": serial_sum, "rounds": rounds,
+           "pool": pool_sum, "serial_plain": serial_sum, "rounds": rounds, "fill_cells": fill,
            "config": {"workload": f"{count} Jacobi3D solve requests, Poisson arrivals at {rate:.2f}/s "
-                                  f"(0.8 x serial capacity), per-axis size U{{32..384}}, 50..2000 sweeps, "
+                                  f"({load} x serial capacity), per-axis size U{{32..384}}, 50..2000 sweeps, "
                                   f"residual every 50, tol 0, budget {budget / 1e9:.0f} GB, "
                                   f"first {warmup} discarded", "dtype": "f64"}}
     print(json.dumps(out), flush=True)
