@@ -37,8 +37,9 @@ def sweep_bytes(problem) -> int:
     """Algorithmic bytes of one fused sweep over all blocks of a problem.
 
     Per block: read and write every interior cell once (16 B/cell), read the
-    six halo faces (8 B/cell, global-boundary faces included), write each
-    face that has a neighbour into that neighbour's halo storage (8 B/cell).
+    six halo faces (8 B/cell, global-boundary faces included: y and z halos
+    are the neighbours' own boundary rows / planes), and write each x face
+    that has a neighbour into that neighbour's x-halo array (8 B/cell).
     """
     from paper_2202_11819_amd import j3d
     nb, ext = j3d.j3d_block_extents(problem)
@@ -48,7 +49,7 @@ def sweep_bytes(problem) -> int:
             for bx, ex in enumerate(ext[0]):
                 faces = [ey * ez, ey * ez, ex * ez, ex * ez, ex * ey, ex * ey]
                 has = [bx > 0, bx + 1 < nb[0], by > 0, by + 1 < nb[1], bz > 0, bz + 1 < nb[2]]
-                total += 16 * ex * ey * ez + 8 * sum(faces) + 8 * sum(f for f, h in zip(faces, has) if h)
+                total += 16 * ex * ey * ez + 8 * sum(faces) + 8 * sum(f for f, h in zip(faces[:2], has[:2]) if h)
     return total
 
 

@@ -119,8 +119,6 @@ __device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, uint32_t off)
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, AUX));
 }
 
-__device__ __forceinline__ void st_cell(char *p, double v) { *reinterpret_cast<double *>(p) = v; }
-
 template <int AUX>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, double v)
 {
@@ -142,21 +140,21 @@ struct Shape {
 
 // Uniform description of one tile (lives in scalar registers).
 struct TileGeo {
-    const char *cur;   // input field, byte address of plane index 0
+    const char *cur;   // input field, byte address of plane index 0 (the z- ghost plane)
     char *nxt;         // output field
-    char *dxm, *dxp;   // neighbours' x-halo arrays of the next iterate (null: none)
-    char *dym, *dyp;   // neighbours' y-halo row 0 / ey+1 at plane index 0 (null: none)
-    char *dzm, *dzp;   // neighbours' z-halo plane (null: none)
+    const char *zlo;   // plane read as z = -1: the own ghost plane, or in the fused
+    const char *zhi;   // sweep the z neighbour's nearest interior plane; likewise z = ez
+    char *dxm, *dxp;   // x-halo arrays (plane index 0) that take this block's x- / x+ face
+    uint32_t xrm, xrp; // bytes of one plane of those arrays (0: no neighbour, nothing stored)
     uint64_t psb;      // plane stride of this block's field, bytes
-    uint64_t psym, psyp;  // plane strides of the y neighbours, bytes
     int ex, ey, ez, pitch;  // pitch: row stride in doubles (>= ex)
     int x0, y0, z0, nxv, nyv, nzv;
-    bool fused, want_res;
+    bool want_res;
 };
 
 template <int TX, int NTY, int RY, int PF, bool FULL>
 __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *__restrict__ hsrc0,
-                                               uint64_t hstep, int hl, double *sm)
+                                               uint64_t hstep, int hl, double *sm, double *xf)
 {
     using S = Shape<TX, NTY, RY, PF>;
     // Register ring of NB planes: while plane k is computed from planes
@@ -164,15 +162,20 @@ __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *_
     // is unrolled NB times so every ring index is a compile-time constant and
     // a load lands in its register without any copy; the slot of plane k-1 is
     // refilled with plane k+PF+2 right after its last use.
+    //
+    // Every global load and store of a step is issued by every lane, without
+    // branches (lanes with nothing to do address outside the resource), and
+    // the steady-state loop is entered only after one peeled round: the
+    // compiler's memory-counter waits then see the same instruction stream on
+    // every path and wait only for the plane that is about to be used, never
+    // for the stores of the previous step.
     constexpr int NB = PF + 3;
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    const int ex = g.ex;
     const uint32_t rowb = (uint32_t)g.pitch * 8u;
-    // Lanes outside a ragged tile stay in lock-step with the others (no
-    // divergent branches around the streaming accesses): their buffer offset
-    // lies outside every resource, so their loads return 0 and their stores
-    // are dropped, and their LDS writes go to a sink after the plane.
+    // Lanes outside a ragged tile stay in lock-step with the others: their
+    // buffer offset lies outside every resource, so their loads return 0 and
+    // their stores are dropped, and their LDS writes go to a sink after the plane.
     constexpr uint32_t kOutside = 0x80000000u;
     bool vr[RY];
     uint32_t off[RY];  // byte offset of this thread's cell of row r inside a plane
@@ -184,11 +187,30 @@ __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *_
         off[r] = vr[r] ? (uint32_t)(g.y0 + ly + 1) * rowb + (uint32_t)(g.x0 + tx) * 8u : kOutside;
         lw[r] = vr[r] ? (ly + 1) * S::LX + tx + 1 : S::LX * S::LY + (tid & 31);
     }
+    // x faces (fused sweep): a cell of the block's first / last column puts its
+    // new value into xf; after the next barrier the first 2*TY threads store one
+    // face cell each, so a plane's face goes out as two coalesced stores.
     const int x = g.x0 + tx;
-    const bool wxm = g.dxm && x == 0, wxp = g.dxp && x == ex - 1;
-    const uint32_t xo = (uint32_t)x * 8u;
+    const bool fxm = g.xrm != 0 && x == 0, fxp = g.xrp != 0 && x == g.ex - 1;
+    const int xs = tid < 2 * S::TY ? tid : 0;  // xf slot this thread stores
+    uint32_t xom = kOutside, xop = kOutside;
+    if (tid < S::TY) {
+        if (tid < g.nyv && g.x0 == 0) xom = (uint32_t)(g.y0 + tid) * 8u;
+    } else if (tid < 2 * S::TY) {
+        if (tid - S::TY < g.nyv && g.x0 + g.nxv == g.ex) xop = (uint32_t)(g.y0 + tid - S::TY) * 8u;
+    }
     const uint64_t psb = g.psb;
     const int zend = g.z0 + g.nzv;  // last plane read: the z+ neighbour of the last one computed
+    auto plane = [&](int z) -> const char * {
+        return z < 0 ? g.zlo : (z >= g.ez ? g.zhi : g.cur + (uint64_t)(z + 1) * psb);
+    };
+    // x faces of plane k, taken from xf buffer `buf`
+    auto store_xfaces = [&](int k, int buf, bool any) __attribute__((always_inline)) {
+        const double xv = xf[buf * 2 * S::TY + xs];
+        const uint64_t fo = any ? (uint64_t)k * g.ey * 8u : 0u;
+        bstore<0>(rsrc(g.dxm + fo, any ? g.xrm : 0u), xom, xv);
+        bstore<0>(rsrc(g.dxp + fo, any ? g.xrp : 0u), xop, xv);
+    };
 
     double R[NB][RY];
     double H[NB];
@@ -196,82 +218,80 @@ __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *_
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
         const int z = g.z0 - 1 + j;
-        H[j] = 0.0;
-        if (z <= zend) {
-            const __amdgpu_buffer_rsrc_t rz = rsrc(g.cur + (uint64_t)(z + 1) * psb, psb);
+        const bool live = z <= zend;
+        const __amdgpu_buffer_rsrc_t rz = rsrc(plane(live ? z : zend), live ? psb : 0);
 #pragma unroll
-            for (int r = 0; r < RY; ++r) R[j][r] = bload<kAuxLoad>(rz, off[r]);
-        } else {
-#pragma unroll
-            for (int r = 0; r < RY; ++r) R[j][r] = 0.0;
-        }
-        if (z >= g.z0 && z < zend) H[j] = hsrc0[(uint64_t)z * hstep];
+        for (int r = 0; r < RY; ++r) R[j][r] = bload<kAuxLoad>(rz, off[r]);
+        const int zh = z < g.z0 ? g.z0 : (z < zend ? z : zend - 1);
+        H[j] = hsrc0[(uint64_t)zh * hstep];
     }
     double rmax = 0.0;
 
-    for (int kb = 0; kb < g.nzv; kb += NB) {
+    auto step = [&](const int kk, const int j) __attribute__((always_inline)) {
+        const int k = g.z0 + kk;
+        const int jm = j, jc = (j + 1) % NB, jp = (j + 2) % NB;
+        double *L = sm + (kk & 1) * S::PLANE;
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const int kk = kb + j;
-            if (kk < g.nzv) {
-                const int k = g.z0 + kk;
-                const int jm = j, jc = (j + 1) % NB, jp = (j + 2) % NB;
-                double *L = sm + (kk & 1) * S::PLANE;
-#pragma unroll
-                for (int r = 0; r < RY; ++r) L[lw[r]] = R[jc][r];
-                if (hl >= 0) L[hl] = H[jc];
-                lds_barrier();
+        for (int r = 0; r < RY; ++r) L[lw[r]] = R[jc][r];
+        if (hl >= 0) L[hl] = H[jc];
+        lds_barrier();
+        store_xfaces(k - 1, (kk + 1) & 1, kk > 0);
 
-                const __amdgpu_buffer_rsrc_t ro = rsrc(g.nxt + (uint64_t)(k + 1) * psb, psb);
+        const __amdgpu_buffer_rsrc_t ro = rsrc(g.nxt + (uint64_t)(k + 1) * psb, psb);
+        double *XF = xf + (kk & 1) * 2 * S::TY;
 #pragma unroll
-                for (int r = 0; r < RY; ++r) {
-                    const int li = (ty + NTY * r + 1) * S::LX + tx + 1;
-                    double s = R[jc][r];
-                    s += L[li - 1];
-                    s += L[li + 1];
-                    s += L[li - S::LX];
-                    s += L[li + S::LX];
-                    s += R[jm][r];
-                    s += R[jp][r];
-                    const double v = s * kW;
-                    bstore<kAuxStore>(ro, off[r], v);
-                    if (g.fused && vr[r]) {
-                        // this block's new face values, straight into the
-                        // neighbours' halo storage of the next iterate
-                        const int y = g.y0 + ty + NTY * r;
-                        if (wxm) st_cell(g.dxm + ((uint64_t)k * g.ey + y) * 8u, v);
-                        if (wxp) st_cell(g.dxp + ((uint64_t)k * g.ey + y) * 8u, v);
-                        if (g.dym && y == 0) st_cell(g.dym + (uint64_t)(k + 1) * g.psym + xo, v);
-                        if (g.dyp && y == g.ey - 1) st_cell(g.dyp + (uint64_t)(k + 1) * g.psyp + xo, v);
-                        if (g.dzm && k == 0) st_cell(g.dzm + off[r], v);
-                        if (g.dzp && k == g.ez - 1) st_cell(g.dzp + off[r], v);
-                    }
-                    if (g.want_res) {
-                        const double d = vr[r] ? fabs(v - R[jc][r]) : 0.0;
-                        rmax = d > rmax ? d : rmax;
-                    }
-                }
-                // refill the slot of plane k-1 with plane k-1+NB; past the
-                // tile's last plane the resource is empty (loads return 0),
-                // so the loads issue unconditionally and the wait counts stay
-                // exact
-                const int zn = k - 1 + NB;
-                {
-                    const bool live = zn <= zend;
-                    const __amdgpu_buffer_rsrc_t rn =
-                        rsrc(g.cur + (uint64_t)((live ? zn : zend) + 1) * psb, live ? psb : 0);
-#pragma unroll
-                    for (int r = 0; r < RY; ++r) R[jm][r] = bload<kAuxLoad>(rn, off[r]);
-                    H[jm] = hsrc0[(uint64_t)(zn < zend ? zn : zend - 1) * hstep];
-                }
+        for (int r = 0; r < RY; ++r) {
+            const int ly = ty + NTY * r;
+            const int li = (ly + 1) * S::LX + tx + 1;
+            double s = R[jc][r];
+            s += L[li - 1];
+            s += L[li + 1];
+            s += L[li - S::LX];
+            s += L[li + S::LX];
+            s += R[jm][r];
+            s += R[jp][r];
+            const double v = s * kW;
+            bstore<kAuxStore>(ro, off[r], v);
+            if (vr[r]) {
+                if (fxm) XF[ly] = v;
+                if (fxp) XF[S::TY + ly] = v;
+            }
+            if (g.want_res) {
+                const double d = vr[r] ? fabs(v - R[jc][r]) : 0.0;
+                rmax = d > rmax ? d : rmax;
             }
         }
+        // refill the slot of plane k-1 with plane k-1+NB; past the tile's
+        // last plane the resource is empty (loads return 0)
+        const int zn = k - 1 + NB;
+        const bool live = zn <= zend;
+        const __amdgpu_buffer_rsrc_t rn = rsrc(plane(live ? zn : zend), live ? psb : 0);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) R[jm][r] = bload<kAuxLoad>(rn, off[r]);
+        H[jm] = hsrc0[(uint64_t)(zn < zend ? zn : zend - 1) * hstep];
+    };
+
+    int kk = 0;
+    if (g.nzv >= NB) {
+        // one peeled round, then the steady state
+#pragma unroll
+        for (int j = 0; j < NB; ++j) step(j, j);
+        for (kk = NB; kk + NB <= g.nzv; kk += NB) {
+#pragma unroll
+            for (int j = 0; j < NB; ++j) step(kk + j, j);
+        }
     }
+#pragma unroll
+    for (int j = 0; j < NB - 1; ++j)
+        if (kk + j < g.nzv) step(kk + j, j);
+    lds_barrier();
+    store_xfaces(zend - 1, (g.nzv - 1) & 1, true);
     return rmax;
 }
 
 template <int TX, int NTY, int RY, int PF>
-__device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, double *sm, double *red)
+__device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, double *sm, double *red,
+                                           double *xf)
 {
     using S = Shape<TX, NTY, RY, PF>;
     const BlockDesc *__restrict__ B = a.blocks + tl.block;
@@ -290,7 +310,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
         p = a.parity;
         g.want_res = (a.flags & SW_RES) != 0;
     }
-    g.fused = (a.flags & SW_FUSED) != 0;
+    const bool fused = (a.flags & SW_FUSED) != 0;
     g.ex = B->ext[0];
     g.ey = B->ext[1];
     g.ez = B->ext[2];
@@ -314,43 +334,63 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
         g.nzv = (int)((int64_t)(tl.tz + 1) * ez / ntz) - g.z0;
     }
 
-    g.dxm = g.dxp = g.dym = g.dyp = g.dzm = g.dzp = nullptr;
-    g.psym = g.psyp = 0;
-    if (g.fused) {
+    // Halo sources.  The unfused sweep reads the block's own ghost layer,
+    // which the unpack step has filled.  The fused sweep reads the y and z
+    // halos straight from the neighbours' current iterate (their rows / planes
+    // next to the shared face: the exchange is a read across the block
+    // boundary, nothing is copied), and hands its x faces, which would be
+    // strided reads for the neighbour, to the neighbours' x-halo arrays of the
+    // next iterate.  Global-boundary faces always come from the own ghost
+    // layer, which holds the Dirichlet values.
+    g.zlo = g.cur;
+    g.zhi = g.cur + (uint64_t)(ez + 1) * g.psb;
+    g.dxm = g.dxp = g.nxt;
+    g.xrm = g.xrp = 0;
+    const uint64_t ps = (uint64_t)(ey + 2) * pitch;  // plane stride, doubles
+    const double *curd = a.base + B->off[p];
+    const double *ym_src = curd + ps + (uint64_t)g.y0 * pitch;                 // row y0-1, plane 0
+    const double *yp_src = curd + ps + (uint64_t)(g.y0 + g.nyv + 1) * pitch;  // row y0+nyv, plane 0
+    uint64_t ym_step = ps, yp_step = ps;
+    if (fused) {
         const int q = p ^ 1;
-        if (B->nbr[0] >= 0) g.dxm = base + (a.blocks[B->nbr[0]].xoff[q] + (int64_t)ey * ez) * 8;
-        if (B->nbr[1] >= 0) g.dxp = base + a.blocks[B->nbr[1]].xoff[q] * 8;
-        if (B->nbr[2] >= 0) {
-            const BlockDesc *N = a.blocks + B->nbr[2];
-            g.psym = (uint64_t)(N->ext[1] + 2) * pitch * 8u;
-            g.dym = base + (N->off[q] + (int64_t)(N->ext[1] + 1) * pitch) * 8;
+        if (B->nbr[0] >= 0) {
+            g.dxm = base + (a.blocks[B->nbr[0]].xoff[q] + (int64_t)ey * ez) * 8;
+            g.xrm = (uint32_t)ey * 8u;
         }
-        if (B->nbr[3] >= 0) {
+        if (B->nbr[1] >= 0) {
+            g.dxp = base + a.blocks[B->nbr[1]].xoff[q] * 8;
+            g.xrp = (uint32_t)ey * 8u;
+        }
+        if (g.y0 == 0 && B->nbr[2] >= 0) {
+            const BlockDesc *N = a.blocks + B->nbr[2];
+            const uint64_t psn = (uint64_t)(N->ext[1] + 2) * pitch;
+            ym_src = a.base + N->off[p] + psn + (uint64_t)N->ext[1] * pitch;
+            ym_step = psn;
+        }
+        if (g.y0 + g.nyv == ey && B->nbr[3] >= 0) {
             const BlockDesc *N = a.blocks + B->nbr[3];
-            g.psyp = (uint64_t)(N->ext[1] + 2) * pitch * 8u;
-            g.dyp = base + N->off[q] * 8;
+            const uint64_t psn = (uint64_t)(N->ext[1] + 2) * pitch;
+            yp_src = a.base + N->off[p] + psn + pitch;
+            yp_step = psn;
         }
         if (B->nbr[4] >= 0) {
             const BlockDesc *N = a.blocks + B->nbr[4];
-            g.dzm = base + N->off[q] * 8 + (uint64_t)(N->ext[2] + 1) * g.psb;
+            g.zlo = base + N->off[p] * 8 + (uint64_t)N->ext[2] * g.psb;
         }
-        if (B->nbr[5] >= 0) g.dzp = base + a.blocks[B->nbr[5]].off[q] * 8;
+        if (B->nbr[5] >= 0) g.zhi = base + a.blocks[B->nbr[5]].off[p] * 8 + g.psb;
     }
 
     // Halo loader role: one ring cell of the LDS plane per thread.  hsrc0
     // points at plane index 0's value; plane k adds k*hstep doubles.
     const int tid = threadIdx.x;
     int hl = -1;
-    const double *hsrc0 = a.base + B->off[p];  // lanes without a halo role read a valid cell
+    const double *hsrc0 = curd;  // lanes without a halo role read a valid cell
     uint64_t hstep = 0;
-    const uint64_t ps = (uint64_t)(ey + 2) * pitch;
-    const double *curd = a.base + B->off[p];
     if (tid < 2 * TX) {
         const int side = tid / TX, xx = tid % TX;
         if (xx < g.nxv) {
-            const int row = side ? (g.y0 + g.nyv) : (g.y0 - 1);  // a halo row at the block edge
-            hsrc0 = curd + ps + (uint64_t)(row + 1) * pitch + g.x0 + xx;
-            hstep = ps;
+            hsrc0 = (side ? yp_src : ym_src) + g.x0 + xx;
+            hstep = side ? yp_step : ym_step;
             hl = (side ? (g.nyv + 1) : 0) * S::LX + xx + 1;
         }
     } else if (tid < 2 * TX + 2 * S::TY) {
@@ -382,8 +422,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
     }
 
     const bool full = g.nxv == TX && g.nyv == S::TY;
-    const double rmax = full ? sweep_planes<TX, NTY, RY, PF, true>(g, hsrc0, hstep, hl, sm)
-                             : sweep_planes<TX, NTY, RY, PF, false>(g, hsrc0, hstep, hl, sm);
+    const double rmax = full ? sweep_planes<TX, NTY, RY, PF, true>(g, hsrc0, hstep, hl, sm, xf)
+                             : sweep_planes<TX, NTY, RY, PF, false>(g, hsrc0, hstep, hl, sm, xf);
 
     if (g.want_res) {
         // max over the workgroup, then one atomic per tile; the maximum of
@@ -411,8 +451,9 @@ __global__ __launch_bounds__(TX *NTY) void sweep_kernel(SweepArgs a)
     using S = Shape<TX, NTY, RY, PF>;
     __shared__ double sm[S::LDS];
     __shared__ double red[S::NT / 64];
+    __shared__ double xf[4 * S::TY];
     const int t = xcd_remap(blockIdx.x, gridDim.x);
-    sweep_tile<TX, NTY, RY, PF>(a, a.tiles[a.tile_begin + t], sm, red);
+    sweep_tile<TX, NTY, RY, PF>(a, a.tiles[a.tile_begin + t], sm, red, xf);
 }
 
 // Persistent form: a grid of a few workgroups per compute unit; per-XCD
@@ -424,6 +465,7 @@ __global__ __launch_bounds__(TX *NTY) void sweep_kernel_persistent(SweepArgs a)
     using S = Shape<TX, NTY, RY, PF>;
     __shared__ double sm[S::LDS];
     __shared__ double red[S::NT / 64];
+    __shared__ double xf[4 * S::TY];
     __shared__ int next_tile;
     const int xcd = blockIdx.x % kXcds;
     for (int qi = 0; qi < kXcds; ++qi) {
@@ -437,7 +479,7 @@ __global__ __launch_bounds__(TX *NTY) void sweep_kernel_persistent(SweepArgs a)
             const int t = next_tile;
             __syncthreads();
             if (t >= end) break;
-            sweep_tile<TX, NTY, RY, PF>(a, a.tiles[a.tile_begin + t], sm, red);
+            sweep_tile<TX, NTY, RY, PF>(a, a.tiles[a.tile_begin + t], sm, red, xf);
             __syncthreads();  // the next tile reuses the LDS
         }
     }
