@@ -821,20 +821,20 @@ constexpr int kMaxGridY = 65535;
     X(256, 4, 4, 1)     \
     X(32, 8, 4, 1)      \
     X(64, 4, 8, 1)      \
-    X(64, 16, 4, 2)     \
+    X(64, 16, 2, 3)     \
     X(64, 8, 4, 2)      \
     X(64, 16, 2, 1)     \
     X(64, 16, 2, 2)     \
     X(64, 4, 8, 2)      \
-    X(128, 4, 8, 2)     \
-    X(256, 4, 4, 2)     \
+    X(128, 4, 4, 2)     \
+    X(128, 8, 2, 3)     \
     X(160, 4, 4, 1)     \
     X(192, 4, 4, 1)     \
-    X(64, 4, 8, 3)      \
+    X(64, 8, 2, 2)      \
     X(64, 4, 4, 2)      \
     X(64, 4, 4, 4)      \
     X(64, 8, 4, 3)      \
-    X(128, 4, 8, 3)     \
+    X(128, 4, 4, 3)     \
     X(128, 4, 4, 4)
 
 struct VariantEntry {

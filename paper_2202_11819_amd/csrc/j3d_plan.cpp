@@ -142,6 +142,10 @@ j3d_status resolve_decomp(const j3d_problem *p, Decomp *d)
                     ex * ez > INT32_MAX || ex * ey > INT32_MAX)
                     return set_error(J3D_EINVAL, "block %lldx%lldx%lld exceeds 2^31 cells with halos",
                                      (long long)ex, (long long)ey, (long long)ez);
+                // the sweep addresses one plane (with its ghost rows) by 32-bit byte offsets
+                if ((ey + 2) * row_pitch(ex) * 8 > INT32_MAX)
+                    return set_error(J3D_EINVAL, "block %lldx%lldx%lld: an x-y plane exceeds 2^28 cells",
+                                     (long long)ex, (long long)ey, (long long)ez);
             }
     return J3D_OK;
 }
@@ -316,15 +320,15 @@ void default_tune(const Plan &plan, int cus, j3d_tune *t)
     if (exm <= 32)
         v = find_variant(32, 32, 256);
     else if (exm <= 64)
-        v = eym <= 16 ? find_variant(64, 16, 256) : find_variant(64, 32, 256);
+        v = eym <= 16 ? find_variant(64, 16, 256) : find_variant(64, 32, 512);
     else if (exm <= 128)
-        v = find_variant(128, 32, 512);
+        v = find_variant(128, 16, 512);
     else if (exm <= 160)
         v = find_variant(160, 16, 640);
     else if (exm <= 192)
         v = find_variant(192, 16, 768);
     else
-        v = find_variant(256, 16, 1024);
+        v = find_variant(128, 32, 1024);  // wider rows: two or more 128-wide tiles per row
     t->variant = v;
     t->blocks_per_cu = 0;
     // z-chunks of 32 planes, unless the block is shallow or the launch would

@@ -92,6 +92,7 @@ def test_block_extents_rules():
     dict(n=(4, 4, 4), bc=(0, 0, 0, float("inf"), 0, 0)),
     dict(n=(2 ** 31, 1, 1)),
     dict(n=(4096, 4096, 4096)),                              # one block beyond 2^31 cells
+    dict(n=(20000, 20000, 1)),                               # one x-y plane beyond 2^28 cells
 ])
 def test_invalid_problems_are_rejected(kwargs):
     p = j3d.Problem(kwargs.pop("n"), **kwargs)
