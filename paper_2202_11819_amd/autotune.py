@@ -10,6 +10,7 @@ the mix, so a later batch of the same class reuses the choice.
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import math
 import os
@@ -66,7 +67,10 @@ def time_batch(problems, iters, tune, stream=None) -> float:
 
 def tune_batch(problems, iters, sample_sweeps=24, cache_path=DEFAULT_CACHE, log=None, force=False):
     """Best (variant, zchunk, blocks_per_cu) for this mix; cached per (arch, size class)."""
-    key = f"{device_arch()}|batch|{size_class(problems)}"
+    # the key names the library build and its tile table, so a cache written
+    # by another build (whose variant indices may mean other shapes) is not used
+    table = hashlib.sha256(repr(j3d.variants()).encode()).hexdigest()[:12]
+    key = f"{device_arch()}|{j3d.j3d_version()}|{table}|batch|{size_class(problems)}"
     cache = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as f:

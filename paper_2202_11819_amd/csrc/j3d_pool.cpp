@@ -24,7 +24,7 @@ namespace {
 
 // 64x32 tiles of 256 threads and 32-plane z-chunks: enough workgroups per
 // request that a round of a few mid-sized requests fills the GPU
-constexpr int kPoolVariantTileX = 64, kPoolVariantTileY = 32, kPoolVariantThreads = 256;
+constexpr int kPoolVariantTileX = 64, kPoolVariantTileY = 32, kPoolVariantThreads = 512;
 constexpr int kPoolZchunk = 32;
 constexpr int64_t kPoolTilesPerReq = 4096;
 
