@@ -126,6 +126,7 @@ def bench_overdecomposed(args):
     if args.tune:
         v, zc, bpc = (int(x) for x in args.tune.split(","))
         s.set_tune(v, zc, bpc)
+    tune = s.get_tune()                   # (variant, zchunk, blocks_per_cu)
     u0 = s.get_interior_device()          # the seeded interior, kept resident in HBM
     stream = torch.cuda.current_stream()
     per_launch = sweep_bytes(s.problem)
@@ -170,7 +171,8 @@ def bench_overdecomposed(args):
         "config": {"workload": f"{n[0]}^3 FP64 grid as {spec.nblk[0]}x{spec.nblk[1]}x{spec.nblk[2]} blocks of "
                                f"{n[0] // spec.nblk[0]}^3, zero Dirichlet boundary, seeded U[0,1) interior, "
                                f"{sweeps} sweeps per step (pack+exchange+unpack+update fused, {args.mode})",
-                   "grid": list(n), "blocks": list(spec.nblk), "sweeps": sweeps, "mode": args.mode},
+                   "grid": list(n), "blocks": list(spec.nblk), "sweeps": sweeps, "mode": args.mode,
+                   "tune": list(tune), "tile": list(j3d.variants()[tune[0]])},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": (round(traffic_bytes / (kernel_ms * 1e-3) / 1e9, 1) if traffic_bytes else None),

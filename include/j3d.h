@@ -152,7 +152,10 @@ j3d_status j3d_arena_bytes(const j3d_problem *p, uint64_t *bytes);
 j3d_status j3d_field_bytes(const j3d_problem *p, uint64_t *bytes);
 
 /* Compiled sweep tile shapes: variant i covers tile_x x tile_y cells of an
- * x-y plane with `threads` threads.  Returns EINVAL past the last variant. */
+ * x-y plane with `threads` threads.  tile_x == 0 marks a flattened variant:
+ * its tiles are whole row segments sized per block (any width, up to tile_y
+ * cells, every thread owning tile_y / threads cells).  Returns EINVAL past
+ * the last variant.                                                          */
 j3d_status j3d_variant_info(int32_t variant, int32_t *tile_x, int32_t *tile_y,
                             int32_t *threads);
 
@@ -175,6 +178,9 @@ j3d_status j3d_set_face(j3d_solver *s, int32_t face, const double *src, int src_
 
 /* Choose the sweep kernel shape (see j3d_tune); NULL restores the default. */
 j3d_status j3d_set_tune(j3d_solver *s, const j3d_tune *t);
+
+/* The shape in use (the default chosen by block size until j3d_set_tune). */
+j3d_status j3d_get_tune(const j3d_solver *s, j3d_tune *out);
 
 /* Enqueue `iters` (>= 0) Jacobi iterations in the given mode.  If residual_out
  * is non-NULL the last sweep's residual is written there and the call

@@ -37,6 +37,10 @@ class Solver:
     def set_tune(self, variant=-1, zchunk=0, blocks_per_cu=0):
         C.j3d_set_tune(self.h, variant, zchunk, blocks_per_cu)
 
+    def get_tune(self):
+        """(variant, zchunk, blocks_per_cu) in use."""
+        return C.j3d_get_tune(self.h)
+
     def set_interior(self, u):
         if isinstance(u, torch.Tensor) and u.is_cuda:
             u = u.contiguous().to(torch.float64)

@@ -76,6 +76,18 @@ void default_tune(const Plan &plan, int cus, j3d_tune *t);
 
 // Number of tiles that variant/zchunk give over the blocks of a plan.
 uint64_t count_tiles(const Plan &plan, int variant, int zchunk);
+// Tiles of a block's x-y plane under variant vi: ntx along x, nty along y.
+inline void tiles_xy(const VariantInfo &vi, int64_t ex, int64_t ey, int64_t *ntx, int64_t *nty)
+{
+    if (vi.tile_x == 0) {
+        const FlatShape s = flat_shape((int)ex, (int)ey, vi.threads, vi.tile_y);
+        *ntx = s.tnx;
+        *nty = s.tny;
+    } else {
+        *ntx = (ex + vi.tile_x - 1) / vi.tile_x;
+        *nty = (ey + vi.tile_y - 1) / vi.tile_y;
+    }
+}
 
 // Validates a tune against a plan; fills the effective z-chunk.
 j3d_status check_tune(const Plan &plan, const j3d_tune *t, int *zchunk_eff);

@@ -17,7 +17,9 @@
 //          contiguous runs instead of one double per row.
 //
 // A global-boundary face holds its Dirichlet values in the same halo storage,
-// written once for both parities; interior faces are written by neighbours.
+// written once for both parities.  For interior faces the unfused modes
+// unpack received faces into this storage; the fused sweep reads y and z
+// halos from the neighbour's field directly and receives only x halos.
 // The unfused modes also use per-block contiguous send and receive buffers
 // S[b], R[b], each the six faces in the order x-, x+, y-, y+, z-, z+ with
 // sizes ey*ez, ey*ez, ex*ez, ex*ez, ex*ey, ex*ey (Fig. 1's send_halo/recv_halo).
@@ -65,7 +67,7 @@ struct Tile {
 };
 
 enum : int32_t {
-    SW_FUSED = 1,   // write new face values into the neighbours' next halo storage
+    SW_FUSED = 1,   // halos from the neighbours (y, z read directly; x faces handed over)
     SW_RES = 2,     // plain mode: residual of this sweep into res[0] (via the block's problem)
     SW_MULTI = 4,   // per-problem activity, parity and residual policy from ProbDesc
     SW_PERSIST = 8  // persistent grid with per-XCD tile queues
@@ -89,11 +91,44 @@ struct SweepArgs {
 
 // ---- kernel variants ----------------------------------------------------------
 
+// tile_x == 0 marks a flattened variant: its tiles cover whole row segments
+// of any width and tile_y is its cell capacity per plane (threads * rows per
+// thread).
 struct VariantInfo {
     int tile_x, tile_y, threads;
+    int prefetch;  // planes of loads in flight beyond the next one
 };
 int variant_count();
 VariantInfo variant_info(int v);
+
+// ---- flattened tiles ------------------------------------------------------------
+// A flattened tile covers nxv x nyv cells of an x-y plane, numbered x fastest
+// and dealt to the threads in that order, so every lane has a cell whatever
+// the block's width.  Per block, x is cut into tnx pieces of at most
+// flat_max_x(nt) columns (each after the first starting on a 16-column
+// boundary, so rows stay cache-line aligned) and y into tny near-equal pieces
+// of at most hy rows, with wx * hy <= cap (cells per thread budget) and
+// 2 * (wx + hy) <= nt (one thread per cell of the tile's halo ring), wx being
+// the widest x piece.  Host and kernels evaluate the same functions.
+struct FlatShape {
+    int tnx, tny, wx, hy;
+};
+constexpr int flat_max_x(int nt) { return nt >= 512 ? 192 : nt / 2 - 32; }
+constexpr FlatShape flat_shape(int ex, int ey, int nt, int cap)
+{
+    const int mx = flat_max_x(nt);
+    const int tnx = (ex + mx - 1) / mx;
+    const int wx = tnx == 1 ? ex : (ex + tnx - 1) / tnx + 15;
+    int hy = cap / wx;
+    if (nt / 2 - wx < hy) hy = nt / 2 - wx;
+    if (ey < hy) hy = ey;
+    if (hy < 1) hy = 1;
+    return FlatShape{tnx, (ey + hy - 1) / hy, wx, hy};
+}
+constexpr int flat_x0(int ex, int tnx, int tx)
+{
+    return tx == 0 ? 0 : tx >= tnx ? ex : (int)(((int64_t)tx * ex / tnx) & ~(int64_t)15);
+}
 
 // ---- launchers (defined in j3d_kernels.hip); all enqueue on `stream` ----------
 // Every launcher returns 0 or a hipError_t value.

@@ -125,17 +125,116 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, d
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(i32x2, v), r, (int)off, 0, AUX);
 }
 
-template <int TX, int NTY, int RY, int PF>
-struct Shape {
-    static constexpr int TY = NTY * RY;   // tile rows
-    static constexpr int NT = TX * NTY;   // threads
-    static constexpr int LX = TX + 2;     // LDS plane with a one-cell ring
-    static constexpr int LY = TY + 2;
-    static constexpr int PLANE = LX * LY + 32;  // plane + a sink for masked lanes
-    static constexpr int LDS = 2 * PLANE;
+// ---- tile layouts ------------------------------------------------------------
+//
+// A tile is a rectangle of one block's x-y plane (x0.., y0.., nxv x nyv cells)
+// streamed over a range of planes.  A layout decides which cell of the
+// rectangle each thread owns in each of its RY rows, and which cell of the
+// rectangle's one-cell halo ring it loads.  The LDS holds the current plane
+// of the rectangle with its ring: row length lx = width + 2.
+
+// Occupancy.  More streams per compute unit were measured slower: two
+// 512-thread workgroups per CU (4 waves per SIMD) sweep 3-15% slower than one,
+// the HBM sees more concurrent, scattered streams for the same bytes.  So a
+// workgroup of 512 threads or more reserves enough LDS to be alone on its CU,
+// and a 256-thread one to share it with at most one other.  The reservation
+// is the tail of the plane buffer, never touched.
+constexpr int kLdsPerCu = 160 * 1024;
+constexpr int smem_doubles(int nt, int used_doubles)
+{
+    const int cap = nt >= 512 ? 1 : 2;                    // workgroups per CU
+    const int need = (kLdsPerCu / (cap + 1) + 1024) / 8;  // more than 1/(cap+1) of the LDS
+    return used_doubles > need ? used_doubles : need;
+}
+
+// Fixed tiles: TX x TY, thread (tx, ty) owns column tx of rows ty + NTY*r.
+// x tiles start on multiples of TX; the last one in a row may be ragged.
+template <int TX, int NTY, int RY_, int PF_>
+struct Tiled {
+    static constexpr int NT = TX * NTY, RY = RY_, PF = PF_;
+    static constexpr int TY = NTY * RY;
+    static constexpr int LXC = TX + 2;
+    static constexpr int SINK = LXC * (TY + 2);    // masked lanes write after the plane
+    static constexpr int PLANE = SINK + 64;
+    static constexpr int XROWS = TY;               // rows of a tile, at most
+    static constexpr int SMEM = smem_doubles(NT, 2 * PLANE);
     static_assert(NT >= 2 * TX + 2 * TY, "every halo cell of a plane needs a loader thread");
     static_assert(NT % 64 == 0, "whole waves");
     static_assert(PF >= 1 && PF <= 4, "prefetch depth");
+    __device__ static int lx(int) { return LXC; }
+    template <bool FULL>
+    __device__ static bool cell(int tid, int r, int nxv, int nyv, int &cx, int &cy)
+    {
+        cx = tid % TX;
+        cy = tid / TX + NTY * r;
+        return FULL || (cx < nxv && cy < nyv);
+    }
+    // ring cell of this thread: kind 0/1 = y-/y+ row (c = column), 2/3 = x-/x+ column (c = row)
+    __device__ static bool ring(int tid, int nxv, int nyv, int &kind, int &c)
+    {
+        if (tid < 2 * TX) {
+            kind = tid / TX;
+            c = tid % TX;
+            return c < nxv;
+        }
+        const int u = tid - 2 * TX;
+        kind = 2 + u / TY;
+        c = u % TY;
+        return u < 2 * TY && c < nyv;
+    }
+    __device__ static void rect(const Tile tl, int ex, int ey, int &x0, int &nxv, int &y0, int &nyv)
+    {
+        const int nty = (ey + TY - 1) / TY;
+        x0 = tl.tx * TX;
+        nxv = min(TX, ex - x0);
+        y0 = (int)((int64_t)tl.ty * ey / nty);
+        nyv = (int)((int64_t)(tl.ty + 1) * ey / nty) - y0;
+    }
+};
+
+// Flattened tiles: the nxv*nyv cells of the rectangle are numbered x fastest
+// and cell f goes to thread f % NT, row f / NT; the rectangle is sized per
+// block by flat_shape, so no lane idles but those of the last partial wave.
+template <int NT_, int RY_, int PF_>
+struct Flat {
+    static constexpr int NT = NT_, RY = RY_, PF = PF_;
+    static constexpr int CAP = NT * RY;
+    // (nxv+2)(nyv+2) <= nxv*nyv + 2(nxv+nyv) + 4 <= CAP + NT + 4
+    static constexpr int SINK = CAP + NT + 4;
+    static constexpr int PLANE = SINK + 64;
+    static constexpr int XROWS = NT / 2;
+    static constexpr int SMEM = smem_doubles(NT, 2 * PLANE);
+    static_assert(NT % 64 == 0 && NT >= 256, "whole waves, room for a halo ring");
+    static_assert(PF >= 1 && PF <= 4, "prefetch depth");
+    __device__ static int lx(int nxv) { return nxv + 2; }
+    template <bool FULL>
+    __device__ static bool cell(int tid, int r, int nxv, int nyv, int &cx, int &cy)
+    {
+        const int f = tid + r * NT;
+        const bool v = f < nxv * nyv;
+        const int q = v ? f / nxv : 0;
+        cy = q;
+        cx = v ? f - q * nxv : 0;
+        return v;
+    }
+    __device__ static bool ring(int tid, int nxv, int nyv, int &kind, int &c)
+    {
+        int h = tid;
+        kind = 0;
+        if (h >= nxv) { h -= nxv; kind = 1; }
+        if (kind == 1 && h >= nxv) { h -= nxv; kind = 2; }
+        if (kind == 2 && h >= nyv) { h -= nyv; kind = 3; }
+        c = h;
+        return kind < 3 || h < nyv;
+    }
+    __device__ static void rect(const Tile tl, int ex, int ey, int &x0, int &nxv, int &y0, int &nyv)
+    {
+        const FlatShape s = flat_shape(ex, ey, NT, CAP);
+        x0 = flat_x0(ex, s.tnx, tl.tx);
+        nxv = flat_x0(ex, s.tnx, tl.tx + 1) - x0;
+        y0 = (int)((int64_t)tl.ty * ey / s.tny);
+        nyv = (int)((int64_t)(tl.ty + 1) * ey / s.tny) - y0;
+    }
 };
 
 // Uniform description of one tile (lives in scalar registers).
@@ -152,11 +251,11 @@ struct TileGeo {
     bool want_res;
 };
 
-template <int TX, int NTY, int RY, int PF, bool FULL>
+template <class K, bool FULL>
 __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *__restrict__ hsrc0,
                                                uint64_t hstep, int hl, double *sm, double *xf)
 {
-    using S = Shape<TX, NTY, RY, PF>;
+    constexpr int RY = K::RY, NT = K::NT;
     // Register ring of NB planes: while plane k is computed from planes
     // k-1, k, k+1, the loads of planes k+2 .. k+1+PF are in flight.  The loop
     // is unrolled NB times so every ring index is a compile-time constant and
@@ -169,35 +268,41 @@ __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *_
     // compiler's memory-counter waits then see the same instruction stream on
     // every path and wait only for the plane that is about to be used, never
     // for the stores of the previous step.
-    constexpr int NB = PF + 3;
+    constexpr int NB = K::PF + 3;
     const int tid = threadIdx.x;
-    const int tx = tid % TX, ty = tid / TX;
+    const int lx = K::lx(g.nxv);
     const uint32_t rowb = (uint32_t)g.pitch * 8u;
-    // Lanes outside a ragged tile stay in lock-step with the others: their
-    // buffer offset lies outside every resource, so their loads return 0 and
-    // their stores are dropped, and their LDS writes go to a sink after the plane.
+    // Lanes without a cell stay in lock-step with the others: their buffer
+    // offset lies outside every resource, so their loads return 0 and their
+    // stores are dropped; their LDS writes go to a sink after the plane and
+    // their LDS reads to a valid cell.
     constexpr uint32_t kOutside = 0x80000000u;
     bool vr[RY];
     uint32_t off[RY];  // byte offset of this thread's cell of row r inside a plane
     int lw[RY];        // LDS slot this thread writes for row r
+    int li[RY];        // LDS slot of the cell (its four in-plane neighbours are +-1, +-lx)
+    int ly[RY];        // row of the cell inside the tile
+    bool fxm[RY], fxp[RY];  // cell on the block's x- / x+ face with a neighbour there (fused)
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-        const int ly = ty + NTY * r;
-        vr[r] = FULL ? true : (tx < g.nxv && ly < g.nyv);
-        off[r] = vr[r] ? (uint32_t)(g.y0 + ly + 1) * rowb + (uint32_t)(g.x0 + tx) * 8u : kOutside;
-        lw[r] = vr[r] ? (ly + 1) * S::LX + tx + 1 : S::LX * S::LY + (tid & 31);
+        int cx, cy;
+        vr[r] = K::template cell<FULL>(tid, r, g.nxv, g.nyv, cx, cy);
+        off[r] = vr[r] ? (uint32_t)(g.y0 + cy + 1) * rowb + (uint32_t)(g.x0 + cx) * 8u : kOutside;
+        li[r] = (cy + 1) * lx + cx + 1;
+        lw[r] = vr[r] ? li[r] : K::SINK + (tid & 63);
+        ly[r] = cy;
+        fxm[r] = vr[r] && g.xrm != 0 && g.x0 + cx == 0;
+        fxp[r] = vr[r] && g.xrp != 0 && g.x0 + cx == g.ex - 1;
     }
     // x faces (fused sweep): a cell of the block's first / last column puts its
-    // new value into xf; after the next barrier the first 2*TY threads store one
-    // face cell each, so a plane's face goes out as two coalesced stores.
-    const int x = g.x0 + tx;
-    const bool fxm = g.xrm != 0 && x == 0, fxp = g.xrp != 0 && x == g.ex - 1;
-    const int xs = tid < 2 * S::TY ? tid : 0;  // xf slot this thread stores
+    // new value into xf; after the next barrier the first 2*nyv threads store
+    // one face cell each, so a plane's face goes out as two coalesced stores.
+    const int xs = tid < g.nyv ? tid : (tid < 2 * g.nyv ? K::XROWS + tid - g.nyv : 0);
     uint32_t xom = kOutside, xop = kOutside;
-    if (tid < S::TY) {
-        if (tid < g.nyv && g.x0 == 0) xom = (uint32_t)(g.y0 + tid) * 8u;
-    } else if (tid < 2 * S::TY) {
-        if (tid - S::TY < g.nyv && g.x0 + g.nxv == g.ex) xop = (uint32_t)(g.y0 + tid - S::TY) * 8u;
+    if (tid < g.nyv) {
+        if (g.x0 == 0) xom = (uint32_t)(g.y0 + tid) * 8u;
+    } else if (tid < 2 * g.nyv) {
+        if (g.x0 + g.nxv == g.ex) xop = (uint32_t)(g.y0 + tid - g.nyv) * 8u;
     }
     const uint64_t psb = g.psb;
     const int zend = g.z0 + g.nzv;  // last plane read: the z+ neighbour of the last one computed
@@ -206,7 +311,7 @@ __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *_
     };
     // x faces of plane k, taken from xf buffer `buf`
     auto store_xfaces = [&](int k, int buf, bool any) __attribute__((always_inline)) {
-        const double xv = xf[buf * 2 * S::TY + xs];
+        const double xv = xf[buf * 2 * K::XROWS + xs];
         const uint64_t fo = any ? (uint64_t)k * g.ey * 8u : 0u;
         bstore<0>(rsrc(g.dxm + fo, any ? g.xrm : 0u), xom, xv);
         bstore<0>(rsrc(g.dxp + fo, any ? g.xrp : 0u), xop, xv);
@@ -230,7 +335,7 @@ __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *_
     auto step = [&](const int kk, const int j) __attribute__((always_inline)) {
         const int k = g.z0 + kk;
         const int jm = j, jc = (j + 1) % NB, jp = (j + 2) % NB;
-        double *L = sm + (kk & 1) * S::PLANE;
+        double *L = sm + (kk & 1) * K::PLANE;
 #pragma unroll
         for (int r = 0; r < RY; ++r) L[lw[r]] = R[jc][r];
         if (hl >= 0) L[hl] = H[jc];
@@ -238,24 +343,21 @@ __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *_
         store_xfaces(k - 1, (kk + 1) & 1, kk > 0);
 
         const __amdgpu_buffer_rsrc_t ro = rsrc(g.nxt + (uint64_t)(k + 1) * psb, psb);
-        double *XF = xf + (kk & 1) * 2 * S::TY;
+        double *XF = xf + (kk & 1) * 2 * K::XROWS;
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
-            const int ly = ty + NTY * r;
-            const int li = (ly + 1) * S::LX + tx + 1;
+            const int c = li[r];
             double s = R[jc][r];
-            s += L[li - 1];
-            s += L[li + 1];
-            s += L[li - S::LX];
-            s += L[li + S::LX];
+            s += L[c - 1];
+            s += L[c + 1];
+            s += L[c - lx];
+            s += L[c + lx];
             s += R[jm][r];
             s += R[jp][r];
             const double v = s * kW;
             bstore<kAuxStore>(ro, off[r], v);
-            if (vr[r]) {
-                if (fxm) XF[ly] = v;
-                if (fxp) XF[S::TY + ly] = v;
-            }
+            if (fxm[r]) XF[ly[r]] = v;
+            if (fxp[r]) XF[K::XROWS + ly[r]] = v;
             if (g.want_res) {
                 const double d = vr[r] ? fabs(v - R[jc][r]) : 0.0;
                 rmax = d > rmax ? d : rmax;
@@ -289,11 +391,10 @@ __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *_
     return rmax;
 }
 
-template <int TX, int NTY, int RY, int PF>
+template <class K>
 __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, double *sm, double *red,
                                            double *xf)
 {
-    using S = Shape<TX, NTY, RY, PF>;
     const BlockDesc *__restrict__ B = a.blocks + tl.block;
     const ProbDesc *__restrict__ P = a.probs + B->prob;
 
@@ -320,17 +421,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
     char *base = reinterpret_cast<char *>(a.base);
     g.cur = base + B->off[p] * 8;
     g.nxt = base + B->off[p ^ 1] * 8;
-    // x tiles start on multiples of TX (rows stay cache-line aligned); y and
-    // z are cut into n = ceil(e / T) near-equal pieces (each <= T), so no
-    // tile is a thin remainder along them.
+    // z is cut into n = ceil(ez / zchunk) near-equal pieces, so no tile is a
+    // thin remainder along it.
+    K::rect(tl, ex, ey, g.x0, g.nxv, g.y0, g.nyv);
     {
-        const int nty = (ey + S::TY - 1) / S::TY;
         const int ntz = (ez + a.zchunk - 1) / a.zchunk;
-        g.x0 = tl.tx * TX;
-        g.nxv = min(TX, ex - g.x0);
-        g.y0 = (int)((int64_t)tl.ty * ey / nty);
         g.z0 = (int)((int64_t)tl.tz * ez / ntz);
-        g.nyv = (int)((int64_t)(tl.ty + 1) * ey / nty) - g.y0;
         g.nzv = (int)((int64_t)(tl.tz + 1) * ez / ntz) - g.z0;
     }
 
@@ -380,50 +476,50 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
         if (B->nbr[5] >= 0) g.zhi = base + a.blocks[B->nbr[5]].off[p] * 8 + g.psb;
     }
 
-    // Halo loader role: one ring cell of the LDS plane per thread.  hsrc0
-    // points at plane index 0's value; plane k adds k*hstep doubles.
+    // Halo loader role: at most one ring cell of the LDS plane per thread.
+    // hsrc0 points at plane index 0's value; plane k adds k*hstep doubles.
     const int tid = threadIdx.x;
+    const int lx = K::lx(g.nxv);
     int hl = -1;
     const double *hsrc0 = curd;  // lanes without a halo role read a valid cell
     uint64_t hstep = 0;
-    if (tid < 2 * TX) {
-        const int side = tid / TX, xx = tid % TX;
-        if (xx < g.nxv) {
-            hsrc0 = (side ? yp_src : ym_src) + g.x0 + xx;
-            hstep = side ? yp_step : ym_step;
-            hl = (side ? (g.nyv + 1) : 0) * S::LX + xx + 1;
-        }
-    } else if (tid < 2 * TX + 2 * S::TY) {
-        const int u = tid - 2 * TX;
-        const int side = u / S::TY, yy = u % S::TY;
-        if (yy < g.nyv) {
-            const int y = g.y0 + yy;
-            if (side == 0) {
-                if (g.x0 == 0) {
-                    hsrc0 = a.base + B->xoff[p] + y;
-                    hstep = ey;
-                } else {
-                    hsrc0 = curd + ps + (uint64_t)(y + 1) * pitch + g.x0 - 1;
-                    hstep = ps;
-                }
-                hl = (yy + 1) * S::LX;
+    {
+        int kind, c;
+        if (K::ring(tid, g.nxv, g.nyv, kind, c)) {
+            if (kind < 2) {
+                hsrc0 = (kind ? yp_src : ym_src) + g.x0 + c;
+                hstep = kind ? yp_step : ym_step;
+                hl = (kind ? (g.nyv + 1) : 0) * lx + c + 1;
             } else {
-                const int xr = g.x0 + g.nxv;
-                if (xr == ex) {
-                    hsrc0 = a.base + B->xoff[p] + (int64_t)ey * ez + y;
-                    hstep = ey;
+                const int y = g.y0 + c;
+                if (kind == 2) {
+                    if (g.x0 == 0) {
+                        hsrc0 = a.base + B->xoff[p] + y;
+                        hstep = ey;
+                    } else {
+                        hsrc0 = curd + ps + (uint64_t)(y + 1) * pitch + g.x0 - 1;
+                        hstep = ps;
+                    }
+                    hl = (c + 1) * lx;
                 } else {
-                    hsrc0 = curd + ps + (uint64_t)(y + 1) * pitch + xr;
-                    hstep = ps;
+                    const int xr = g.x0 + g.nxv;
+                    if (xr == ex) {
+                        hsrc0 = a.base + B->xoff[p] + (int64_t)ey * ez + y;
+                        hstep = ey;
+                    } else {
+                        hsrc0 = curd + ps + (uint64_t)(y + 1) * pitch + xr;
+                        hstep = ps;
+                    }
+                    hl = (c + 1) * lx + g.nxv + 1;
                 }
-                hl = (yy + 1) * S::LX + g.nxv + 1;
             }
         }
     }
 
-    const bool full = g.nxv == TX && g.nyv == S::TY;
-    const double rmax = full ? sweep_planes<TX, NTY, RY, PF, true>(g, hsrc0, hstep, hl, sm, xf)
-                             : sweep_planes<TX, NTY, RY, PF, false>(g, hsrc0, hstep, hl, sm, xf);
+    const int cells = g.nxv * g.nyv;
+    const bool full = cells == K::NT * K::RY;
+    const double rmax = full ? sweep_planes<K, true>(g, hsrc0, hstep, hl, sm, xf)
+                             : sweep_planes<K, false>(g, hsrc0, hstep, hl, sm, xf);
 
     if (g.want_res) {
         // max over the workgroup, then one atomic per tile; the maximum of
@@ -439,33 +535,31 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
         __syncthreads();
         if (tid == 0) {
             double w = 0.0;
-            for (int i = 0; i < S::NT / 64; ++i) w = red[i] > w ? red[i] : w;
+            for (int i = 0; i < K::NT / 64; ++i) w = red[i] > w ? red[i] : w;
             atomic_max_agent(a.res + P->res_slot, (unsigned long long)__double_as_longlong(w));
         }
     }
 }
 
-template <int TX, int NTY, int RY, int PF>
-__global__ __launch_bounds__(TX *NTY) void sweep_kernel(SweepArgs a)
+template <class K>
+__global__ __launch_bounds__(K::NT) void sweep_kernel(SweepArgs a)
 {
-    using S = Shape<TX, NTY, RY, PF>;
-    __shared__ double sm[S::LDS];
-    __shared__ double red[S::NT / 64];
-    __shared__ double xf[4 * S::TY];
+    __shared__ double sm[K::SMEM];
+    __shared__ double red[K::NT / 64];
+    __shared__ double xf[4 * K::XROWS];
     const int t = xcd_remap(blockIdx.x, gridDim.x);
-    sweep_tile<TX, NTY, RY, PF>(a, a.tiles[a.tile_begin + t], sm, red, xf);
+    sweep_tile<K>(a, a.tiles[a.tile_begin + t], sm, red, xf);
 }
 
 // Persistent form: a grid of a few workgroups per compute unit; per-XCD
 // queues over contiguous tile ranges; a workgroup drains its own XCD's
 // queue, then helps the others.
-template <int TX, int NTY, int RY, int PF>
-__global__ __launch_bounds__(TX *NTY) void sweep_kernel_persistent(SweepArgs a)
+template <class K>
+__global__ __launch_bounds__(K::NT) void sweep_kernel_persistent(SweepArgs a)
 {
-    using S = Shape<TX, NTY, RY, PF>;
-    __shared__ double sm[S::LDS];
-    __shared__ double red[S::NT / 64];
-    __shared__ double xf[4 * S::TY];
+    __shared__ double sm[K::SMEM];
+    __shared__ double red[K::NT / 64];
+    __shared__ double xf[4 * K::XROWS];
     __shared__ int next_tile;
     const int xcd = blockIdx.x % kXcds;
     for (int qi = 0; qi < kXcds; ++qi) {
@@ -479,7 +573,7 @@ __global__ __launch_bounds__(TX *NTY) void sweep_kernel_persistent(SweepArgs a)
             const int t = next_tile;
             __syncthreads();
             if (t >= end) break;
-            sweep_tile<TX, NTY, RY, PF>(a, a.tiles[a.tile_begin + t], sm, red, xf);
+            sweep_tile<K>(a, a.tiles[a.tile_begin + t], sm, red, xf);
             __syncthreads();  // the next tile reuses the LDS
         }
     }
@@ -808,45 +902,65 @@ int grid_for(int64_t work, int per_block, int cap)
 
 constexpr int kMaxGridY = 65535;
 
-// Variant table: (TX, NTY, RY, PF).  Tile = TX x (NTY*RY) cells, TX*NTY
-// threads, loads of PF planes beyond the next one in flight.
-#define J3D_VARIANTS(X) \
-    X(64, 16, 4, 1)     \
-    X(64, 8, 8, 1)      \
-    X(64, 4, 4, 1)      \
-    X(64, 8, 4, 1)      \
-    X(128, 8, 4, 1)     \
-    X(128, 4, 8, 1)     \
-    X(128, 4, 4, 1)     \
-    X(256, 4, 4, 1)     \
-    X(32, 8, 4, 1)      \
-    X(64, 4, 8, 1)      \
-    X(64, 16, 2, 3)     \
-    X(64, 8, 4, 2)      \
-    X(64, 16, 2, 1)     \
-    X(64, 16, 2, 2)     \
-    X(64, 4, 8, 2)      \
-    X(128, 4, 4, 2)     \
-    X(128, 8, 2, 3)     \
-    X(160, 4, 4, 1)     \
-    X(192, 4, 4, 1)     \
-    X(64, 8, 2, 2)      \
-    X(64, 4, 4, 2)      \
-    X(64, 4, 4, 4)      \
-    X(64, 8, 4, 3)      \
-    X(128, 4, 4, 3)     \
-    X(128, 4, 4, 4)
+// Variant table.  Fixed tiles (TX, NTY, RY, PF): TX x (NTY*RY) cells, TX*NTY
+// threads, loads of PF planes beyond the next one in flight.  Flattened tiles
+// (NT, RY, PF): NT threads, up to NT*RY cells of whole row segments.  The
+// indices are part of the tuning interface: append, never reorder.
+#define J3D_VARIANTS(X, F) \
+    X(64, 16, 4, 1)        \
+    X(64, 8, 8, 1)         \
+    X(64, 4, 4, 1)         \
+    X(64, 8, 4, 1)         \
+    X(128, 8, 4, 1)        \
+    X(128, 4, 8, 1)        \
+    X(128, 4, 4, 1)        \
+    X(256, 4, 4, 1)        \
+    X(32, 8, 4, 1)         \
+    X(64, 4, 8, 1)         \
+    X(64, 16, 2, 3)        \
+    X(64, 8, 4, 2)         \
+    X(64, 16, 2, 1)        \
+    X(64, 16, 2, 2)        \
+    X(64, 4, 8, 2)         \
+    X(128, 4, 4, 2)        \
+    X(128, 8, 2, 3)        \
+    X(160, 4, 4, 1)        \
+    X(192, 4, 4, 1)        \
+    X(64, 8, 2, 2)         \
+    X(64, 4, 4, 2)         \
+    X(64, 4, 4, 4)         \
+    X(64, 8, 4, 3)         \
+    X(128, 4, 4, 3)        \
+    X(128, 4, 4, 4)        \
+    F(512, 4, 1)           \
+    F(512, 4, 2)           \
+    F(256, 8, 1)           \
+    F(1024, 2, 2)          \
+    F(512, 2, 2)           \
+    F(256, 4, 1)           \
+    F(512, 2, 1)           \
+    F(512, 2, 3)           \
+    F(512, 1, 2)           \
+    F(1024, 1, 2)          \
+    F(256, 2, 2)           \
+    F(1024, 1, 3)          \
+    F(512, 1, 3)
 
 struct VariantEntry {
-    int tx, nty, ry, pf;
+    int tile_x, tile_y, threads;  // tile_x 0: flattened, tile_y its cell capacity
+    int prefetch;
     void (*fn)(SweepArgs);
     void (*persistent)(SweepArgs);
 };
 
-#define J3D_ENTRY(TX, NTY, RY, PF) \
-    {TX, NTY, RY, PF, sweep_kernel<TX, NTY, RY, PF>, sweep_kernel_persistent<TX, NTY, RY, PF>},
-const VariantEntry kVariants[] = {J3D_VARIANTS(J3D_ENTRY)};
-#undef J3D_ENTRY
+#define J3D_TILED(TX, NTY, RY, PF)                                                          \
+    {TX, NTY * RY, TX * NTY, PF, sweep_kernel<Tiled<TX, NTY, RY, PF>>,                      \
+     sweep_kernel_persistent<Tiled<TX, NTY, RY, PF>>},
+#define J3D_FLAT(NT, RY, PF) \
+    {0, NT * RY, NT, PF, sweep_kernel<Flat<NT, RY, PF>>, sweep_kernel_persistent<Flat<NT, RY, PF>>},
+const VariantEntry kVariants[] = {J3D_VARIANTS(J3D_TILED, J3D_FLAT)};
+#undef J3D_TILED
+#undef J3D_FLAT
 constexpr int kVariantCount = sizeof(kVariants) / sizeof(kVariants[0]);
 
 }  // namespace
@@ -856,14 +970,14 @@ int variant_count() { return kVariantCount; }
 VariantInfo variant_info(int v)
 {
     const VariantEntry &e = kVariants[v];
-    return VariantInfo{e.tx, e.nty * e.ry, e.tx * e.nty};
+    return VariantInfo{e.tile_x, e.tile_y, e.threads, e.prefetch};
 }
 
 int launch_sweep(int variant, const SweepArgs &a, int grid, void *stream)
 {
     if (variant < 0 || variant >= kVariantCount || grid < 1) return (int)hipErrorInvalidValue;
     const VariantEntry &e = kVariants[variant];
-    hipLaunchKernelGGL((a.flags & SW_PERSIST) ? e.persistent : e.fn, dim3(grid), dim3(e.tx * e.nty), 0,
+    hipLaunchKernelGGL((a.flags & SW_PERSIST) ? e.persistent : e.fn, dim3(grid), dim3(e.threads), 0,
                        (hipStream_t)stream, a);
     return (int)hipGetLastError();
 }

@@ -169,7 +169,16 @@ int find_variant(int tile_x, int tile_y, int threads)
         const VariantInfo vi = variant_info(v);
         if (vi.tile_x == tile_x && vi.tile_y == tile_y && vi.threads == threads) return v;
     }
-    return 0;
+    return -1;
+}
+
+int find_flat_variant(int threads, int cells, int prefetch)
+{
+    for (int v = 0; v < variant_count(); ++v) {
+        const VariantInfo vi = variant_info(v);
+        if (vi.tile_x == 0 && vi.tile_y == cells && vi.threads == threads && vi.prefetch == prefetch) return v;
+    }
+    return -1;
 }
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -188,9 +197,11 @@ uint64_t count_tiles(const Plan &plan, int variant, int zchunk)
     const VariantInfo vi = variant_info(variant);
     const int zc = zchunk > 0 ? zchunk : max_ez(plan, 0, (int32_t)plan.blocks.size());
     uint64_t n = 0;
-    for (const BlockDesc &B : plan.blocks)
-        n += (uint64_t)(ceil_div(B.ext[0], vi.tile_x) * ceil_div(B.ext[1], vi.tile_y) *
-                        ceil_div(B.ext[2], zc));
+    for (const BlockDesc &B : plan.blocks) {
+        int64_t ntx, nty;
+        tiles_xy(vi, B.ext[0], B.ext[1], &ntx, &nty);
+        n += (uint64_t)(ntx * nty * ceil_div(B.ext[2], zc));
+    }
     return n;
 }
 
@@ -297,12 +308,12 @@ void make_tiles(const Plan &plan, int32_t b0, int32_t b1, int variant, int zchun
     for (int32_t b = b0; b < b1; ++b) {
         const BlockDesc &B = plan.blocks[b];
         if (block_first) block_first->push_back((int32_t)tiles->size());
-        const int ntx = (int)ceil_div(B.ext[0], vi.tile_x);
-        const int nty = (int)ceil_div(B.ext[1], vi.tile_y);
+        int64_t ntx, nty;
+        tiles_xy(vi, B.ext[0], B.ext[1], &ntx, &nty);
         const int ntz = (int)ceil_div(B.ext[2], zc);
         for (int tz = 0; tz < ntz; ++tz)
-            for (int ty = 0; ty < nty; ++ty)
-                for (int tx = 0; tx < ntx; ++tx) tiles->push_back(Tile{b, tx, ty, tz});
+            for (int ty = 0; ty < (int)nty; ++ty)
+                for (int tx = 0; tx < (int)ntx; ++tx) tiles->push_back(Tile{b, tx, ty, tz});
     }
     if (block_first) block_first->push_back((int32_t)tiles->size());
 }
@@ -310,31 +321,37 @@ void make_tiles(const Plan &plan, int32_t b0, int32_t b1, int variant, int zchun
 void default_tune(const Plan &plan, int cus, j3d_tune *t)
 {
     // Shapes measured fastest on MI355X for each block width (one workgroup
-    // per tile; the persistent schedule never won for a single problem).
-    int exm = 1, eym = 1;
-    for (const BlockDesc &B : plan.blocks) {
-        exm = std::max(exm, B.ext[0]);
-        eym = std::max(eym, B.ext[1]);
-    }
-    int v;
-    if (exm <= 32)
-        v = find_variant(32, 32, 256);
-    else if (exm <= 64)
-        v = eym <= 16 ? find_variant(64, 16, 256) : find_variant(64, 32, 512);
-    else if (exm <= 128)
+    // per tile; the persistent schedule never won for a single problem):
+    //   <= 64 wide: flattened tiles of 512 threads, 2 cells each (64 x 16 on
+    //               64-wide blocks), through 64 planes;
+    //   <= 128:     128 x 16 tiles of 512 threads, z-chunks of 32;
+    //   <= 160/192: a tile as wide as the widest block;
+    //   wider:      128 x 32 tiles of 1024 threads, z-chunks of 64.
+    int exm = 1;
+    for (const BlockDesc &B : plan.blocks) exm = std::max(exm, B.ext[0]);
+    int v, zc;
+    if (exm <= 64) {
+        v = find_flat_variant(512, 1024, 3);
+        zc = 64;
+    } else if (exm <= 128) {
         v = find_variant(128, 16, 512);
-    else if (exm <= 160)
+        zc = 32;
+    } else if (exm <= 160) {
         v = find_variant(160, 16, 640);
-    else if (exm <= 192)
+        zc = 32;
+    } else if (exm <= 192) {
         v = find_variant(192, 16, 768);
-    else
-        v = find_variant(128, 32, 1024);  // wider rows: two or more 128-wide tiles per row
+        zc = 32;
+    } else {
+        v = find_variant(128, 32, 1024);
+        zc = 64;
+    }
+    if (v < 0) v = 0;  // a shape missing from the table: any variant is correct, only slower
     t->variant = v;
     t->blocks_per_cu = 0;
-    // z-chunks of 32 planes, unless the block is shallow or the launch would
-    // then have too few workgroups to fill the chip
+    // a shallower chunk if the launch would otherwise have too few workgroups
+    // to fill the chip
     const int ezm = max_ez(plan, 0, (int32_t)plan.blocks.size());
-    int zc = ezm >= 48 ? 32 : ezm;
     while (zc > 16 && count_tiles(plan, v, zc) < (uint64_t)(2 * (cus > 0 ? cus : 256))) zc = (zc + 1) / 2;
     t->zchunk = zc >= ezm ? 0 : zc;
 }

@@ -288,8 +288,9 @@ j3d_status j3d_pool_admit(j3d_pool *pl, const j3d_problem *p, int64_t max_iters,
     j3d_status st = request_geometry(p, &d, &bytes);
     if (st != J3D_OK) return st;
     const VariantInfo vi = variant_info(pl->variant);
-    const int64_t tiles = ((d.n[0] + vi.tile_x - 1) / vi.tile_x) * ((d.n[1] + vi.tile_y - 1) / vi.tile_y) *
-                          ((d.n[2] + kPoolZchunk - 1) / kPoolZchunk);
+    int64_t ntx, nty;
+    tiles_xy(vi, d.n[0], d.n[1], &ntx, &nty);
+    const int64_t tiles = ntx * nty * ((d.n[2] + kPoolZchunk - 1) / kPoolZchunk);
     if (tiles > kPoolTilesPerReq)
         return set_error(J3D_EINVAL, "request of %lldx%lldx%lld needs %lld tiles, more than %lld",
                          (long long)d.n[0], (long long)d.n[1], (long long)d.n[2], (long long)tiles,

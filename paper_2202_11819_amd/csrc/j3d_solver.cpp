@@ -456,6 +456,13 @@ j3d_status j3d_set_tune(j3d_solver *s, const j3d_tune *t)
     return apply_tune(s, d);
 }
 
+j3d_status j3d_get_tune(const j3d_solver *s, j3d_tune *out)
+{
+    if (!s || !out) return set_error(J3D_EINVAL, "NULL argument");
+    *out = s->tune;
+    return J3D_OK;
+}
+
 j3d_status j3d_run(j3d_solver *s, int64_t iters, j3d_mode mode, double *residual_out)
 {
     if (!s) return set_error(J3D_EINVAL, "solver is NULL");

@@ -85,6 +85,7 @@ _SIGS = {
     "j3d_set_interior": ([_H, c_void_p, c_int], c_int),
     "j3d_set_face": ([_H, c_int32, c_void_p, c_int], c_int),
     "j3d_set_tune": ([_H, POINTER(j3d_tune)], c_int),
+    "j3d_get_tune": ([_H, POINTER(j3d_tune)], c_int),
     "j3d_run": ([_H, c_int64, c_int, _DP], c_int),
     "j3d_iters_done": ([_H, POINTER(c_int64)], c_int),
     "j3d_get_interior": ([_H, c_void_p, c_int], c_int),
@@ -233,6 +234,12 @@ def j3d_set_tune(h, variant=-1, zchunk=0, blocks_per_cu=0, default=False):
         return
     t = j3d_tune(int(variant), int(zchunk), int(blocks_per_cu))
     _check(_lib.j3d_set_tune(h, byref(t)), "j3d_set_tune")
+
+
+def j3d_get_tune(h):
+    t = j3d_tune()
+    _check(_lib.j3d_get_tune(h, byref(t)), "j3d_get_tune")
+    return t.variant, t.zchunk, t.blocks_per_cu
 
 
 def j3d_run(h, iters: int, mode, want_residual: bool = False):

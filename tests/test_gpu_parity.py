@@ -294,3 +294,21 @@ def test_uneven_1024_sampled_cells(env):
         vals = u[[c[2] for c in cells], [c[1] for c in cells], [c[0] for c in cells]].cpu().numpy()
     for v, (i, j, k) in zip(vals, cells):
         assert v == oracle.cell_after(spec.n, spec.seed, 0, (0.0,) * 6, t, i, j, k), (i, j, k)
+
+
+def test_tune_roundtrip_and_default_shapes(env):
+    _, api, j3d = env
+    vs = j3d.variants()
+    with api.Solver((512, 512, 512), nblk=(8, 8, 8), seed=1) as s:
+        v, zc, bpc = s.get_tune()
+        # 64-wide blocks default to flattened tiles of 512 threads through whole blocks
+        assert vs[v][0] == 0 and vs[v][2] == 512 and zc == 0 and bpc == 0
+        s.set_tune(3, 16, 2)
+        assert s.get_tune() == (3, 16, 2)
+        s.set_tune(-1, 32, 0)  # -1: the default shape with the given chunking
+        assert s.get_tune()[1:] == (32, 0) and s.get_tune()[0] == v
+    # the default shape for other block widths
+    for n, nblk, tile in [((256, 256, 256), (2, 2, 2), (128, 16, 512)), ((320, 64, 64), (2, 1, 1), (160, 16, 640)),
+                          ((384, 64, 64), (2, 1, 1), (192, 16, 768)), ((256, 64, 64), (1, 1, 1), (128, 32, 1024))]:
+        with api.Solver(n, nblk=nblk, seed=1) as s:
+            assert tuple(vs[s.get_tune()[0]]) == tile, (n, nblk)

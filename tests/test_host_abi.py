@@ -120,9 +120,15 @@ def test_arena_covers_fields_and_grows():
 def test_variant_table():
     vs = j3d.variants()
     assert len(vs) >= 8
+    flat = 0
     for tx, ty, threads in vs:
         assert threads % 64 == 0 and threads <= 1024
-        assert tx % 32 == 0 and 32 <= tx <= 256 and ty >= 16
+        if tx == 0:  # flattened: ty is the cell capacity, a whole number of cells per thread
+            flat += 1
+            assert threads >= 256 and ty % threads == 0
+        else:
+            assert tx % 32 == 0 and 32 <= tx <= 256 and ty >= 16
+    assert flat >= 1
     with pytest.raises(j3d.J3DError):
         j3d.j3d_variant_info(len(vs))
 
