@@ -275,6 +275,7 @@ def main():
     ap.add_argument("--retune", action="store_true", help="batch workload: ignore the tuning cache")
     ap.add_argument("--load", type=float, default=0.8, help="serve workload: arrival rate / serial capacity")
     ap.add_argument("--fill-cells", type=int, default=-1, help="serve workload: pool round policy (-1: default)")
+    ap.add_argument("--pool-tune", default="", help="serve workload: variant,zchunk of the pool's rounds")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "

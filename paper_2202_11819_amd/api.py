@@ -143,6 +143,10 @@ class Pool:
     def set_policy(self, fill_cells, max_wait_rounds=32):
         C.j3d_pool_set_policy(self.h, fill_cells, max_wait_rounds)
 
+    def set_tune(self, variant=-1, zchunk=32):
+        """Tile shape of the rounds; only while no request is admitted."""
+        C.j3d_pool_set_tune(self.h, variant, zchunk)
+
     def poll(self):
         return C.j3d_pool_poll(self.h, self.max_slots)
 

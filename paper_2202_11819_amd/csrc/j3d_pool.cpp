@@ -105,7 +105,7 @@ struct j3d_pool {
     int32_t max_slots = 0;
     hipStream_t stream = nullptr, copy_stream = nullptr;
     Layout lay{};
-    int variant = 0, cus = 256;
+    int variant = 0, zchunk = kPoolZchunk, cus = 256;
     std::vector<Req> reqs;
     std::map<uint64_t, uint64_t> free_ranges;  // offset -> size, within the budget
     bool round_busy = false;
@@ -168,7 +168,7 @@ SweepArgs pool_args(j3d_pool *pl)
     a.tiles = reinterpret_cast<const Tile *>(pl->arena + pl->lay.off_tiles);
     a.res = reinterpret_cast<unsigned long long *>(pl->arena + pl->lay.off_res);
     a.queue = reinterpret_cast<unsigned int *>(pl->arena + pl->lay.off_queue);
-    a.zchunk = kPoolZchunk;
+    a.zchunk = pl->zchunk;
     a.flags = SW_FUSED | SW_MULTI;
     return a;
 }
@@ -290,7 +290,7 @@ j3d_status j3d_pool_admit(j3d_pool *pl, const j3d_problem *p, int64_t max_iters,
     const VariantInfo vi = variant_info(pl->variant);
     int64_t ntx, nty;
     tiles_xy(vi, d.n[0], d.n[1], &ntx, &nty);
-    const int64_t tiles = ntx * nty * ((d.n[2] + kPoolZchunk - 1) / kPoolZchunk);
+    const int64_t tiles = ntx * nty * ((d.n[2] + pl->zchunk - 1) / pl->zchunk);
     if (tiles > kPoolTilesPerReq)
         return set_error(J3D_EINVAL, "request of %lldx%lldx%lld needs %lld tiles, more than %lld",
                          (long long)d.n[0], (long long)d.n[1], (long long)d.n[2], (long long)tiles,
@@ -410,7 +410,7 @@ j3d_status j3d_pool_step(j3d_pool *pl, int32_t sweeps)
         Plan one;
         one.blocks.assign(1, r.blk);
         std::vector<Tile> t;
-        make_tiles(one, 0, 1, pl->variant, kPoolZchunk, &t, nullptr);
+        make_tiles(one, 0, 1, pl->variant, pl->zchunk, &t, nullptr);
         for (Tile &x : t) x.block = s;
         tiles.insert(tiles.end(), t.begin(), t.end());
     }
@@ -513,6 +513,26 @@ j3d_status j3d_pool_set_policy(j3d_pool *pl, int64_t fill_cells, int32_t max_wai
                          max_wait_rounds);
     pl->fill_cells = fill_cells;
     pl->max_wait = max_wait_rounds;
+    return J3D_OK;
+}
+
+j3d_status j3d_pool_set_tune(j3d_pool *pl, const j3d_tune *t)
+{
+    if (!pl) return set_error(J3D_EINVAL, "pool is NULL");
+    for (const Req &r : pl->reqs)
+        if (r.state != R_FREE) return set_error(J3D_ESTATE, "pool tile shape can change only while the pool is empty");
+    int v = pool_variant(), zc = kPoolZchunk;
+    if (t) {
+        if (t->variant < -1 || t->variant >= variant_count())
+            return set_error(J3D_EINVAL, "tune variant %d out of range [-1, %d)", t->variant, variant_count());
+        if (t->zchunk < 1) return set_error(J3D_EINVAL, "pool zchunk %d < 1", t->zchunk);
+        if (t->blocks_per_cu != 0)
+            return set_error(J3D_EINVAL, "the pool launches one workgroup per tile (blocks_per_cu must be 0)");
+        if (t->variant >= 0) v = t->variant;
+        zc = t->zchunk;
+    }
+    pl->variant = v;
+    pl->zchunk = zc;
     return J3D_OK;
 }
 

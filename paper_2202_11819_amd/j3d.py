@@ -102,6 +102,7 @@ _SIGS = {
     "j3d_pool_admit": ([_H, _P, c_int64, c_double, c_int32, c_void_p, POINTER(c_int32)], c_int),
     "j3d_pool_step": ([_H, c_int32], c_int),
     "j3d_pool_set_policy": ([_H, c_int64, c_int32], c_int),
+    "j3d_pool_set_tune": ([_H, POINTER(j3d_tune)], c_int),
     "j3d_pool_poll": ([_H, POINTER(c_int32), c_int32, POINTER(c_int32), POINTER(c_int32)], c_int),
     "j3d_pool_result": ([_H, c_int32, _DP, POINTER(c_int64)], c_int),
     "j3d_pool_release": ([_H, c_int32], c_int),
@@ -351,6 +352,14 @@ def j3d_pool_try_admit(h, p: Problem, max_iters, tol, check_every, host_result_p
 
 def j3d_pool_step(h, sweeps: int):
     _check(_lib.j3d_pool_step(h, int(sweeps)), "j3d_pool_step")
+
+
+def j3d_pool_set_tune(h, variant=-1, zchunk=32, default=False):
+    if default:
+        _check(_lib.j3d_pool_set_tune(h, None), "j3d_pool_set_tune")
+        return
+    t = j3d_tune(int(variant), int(zchunk), 0)
+    _check(_lib.j3d_pool_set_tune(h, byref(t)), "j3d_pool_set_tune")
 
 
 def j3d_pool_set_policy(h, fill_cells: int, max_wait_rounds: int = 32):

@@ -104,12 +104,19 @@ def _requests(W, count=12, seed=4, spread=0.02):
     return out
 
 
-def test_pool_requests_match_oracle_and_solo_runs(env):
+def _flat_variant(j3d):
+    return [i for i, v in enumerate(j3d.variants()) if v[0] == 0][0]
+
+
+@pytest.mark.parametrize("tune", [None, "flat", (8, 16)])
+def test_pool_requests_match_oracle_and_solo_runs(env, tune):
     oracle, api, j3d, W = env
     from paper_2202_11819_amd import serve
+    if tune == "flat":
+        tune = (_flat_variant(j3d), 64)
     trace = _requests(W)
     recs, rounds = serve.serve_pool(trace, budget_bytes=2 << 30, max_slots=8, round_sweeps=50,
-                                    check_every=50, keep_results=True)
+                                    check_every=50, keep_results=True, tune=tune)
     assert rounds > 1
     for r, req in zip(recs, trace):
         s = req.spec
@@ -120,7 +127,7 @@ def test_pool_requests_match_oracle_and_solo_runs(env):
     # alone in a pool of its own: the same bits
     for req in trace[:4]:
         alone, _ = serve.serve_pool([W.Request(arrival=0.0, spec=req.spec)], budget_bytes=1 << 30,
-                                    max_slots=1, keep_results=True)
+                                    max_slots=1, keep_results=True, tune=tune)
         mixed = recs[trace.index(req)]
         assert np.array_equal(alone[0]["u"], mixed["u"]) and alone[0]["residual"] == mixed["residual"]
 
@@ -145,6 +152,28 @@ def test_pool_early_exit_matches_checked_oracle(env):
         assert it == done and r == want_r
         assert np.array_equal(u, want)
         pool.release(slot)
+
+
+def test_pool_tune_only_while_empty(env):
+    _, api, j3d, _ = env
+    with api.Pool(1 << 30, max_slots=2) as pool:
+        pool.set_tune(_flat_variant(j3d), 64)
+        slot = pool.try_admit(j3d.Problem((20, 12, 9), seed=1), 3)
+        with pytest.raises(j3d.J3DError) as e:
+            pool.set_tune(3, 32)
+        assert e.value.status == j3d.J3D_ESTATE
+        while True:
+            done, busy = pool.poll()
+            if slot in done:
+                break
+            if not busy:
+                pool.step(50)
+        pool.release(slot)
+        pool.set_tune(3, 32)
+        for bad in [(len(j3d.variants()), 32), (3, 0)]:
+            with pytest.raises(j3d.J3DError) as e:
+                pool.set_tune(*bad)
+            assert e.value.status == j3d.J3D_EINVAL
 
 
 def test_pool_admission_limits_and_errors(env):
