@@ -227,7 +227,7 @@ def bench_modes(args):
 def bench_sweep(args):
     """1024^3 at several decompositions: GLUP/s and effective GB/s vs block count."""
     import torch
-    from paper_2202_11819_amd import api
+    from paper_2202_11819_amd import api, j3d
     from paper_2202_11819_amd import workloads as W
 
     for label, spec in W.block_sweep(iters=args.sweep_iters):
@@ -249,9 +249,12 @@ def bench_sweep(args):
                           "blocks": nblocks, "value": round(cells * spec.iters / ms / 1e6, 3), "unit": "GLUP/s",
                           "GBps": round(gbps, 1), "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4),
                           "B_per_LUP": round(per / cells, 3), "sweeps": spec.iters,
-                          "ms_per_sweep": round(ms / spec.iters, 4)}), flush=True)
+                          "ms_per_sweep": round(ms / spec.iters, 4), "tune": list(s.get_tune()),
+                          "tile": list(j3d.variants()[s.get_tune()[0]])}), flush=True)
         s.close()
         torch.cuda.empty_cache()
+    if not args.no_copy:  # the copy kernel of known size also calibrates counter runs of this workload
+        print(json.dumps({"metric": "streaming copy, 2 GiB", "copy_GBps": round(copy_bandwidth(), 1)}), flush=True)
 
 
 def main():
