@@ -98,19 +98,36 @@ def cpu_baseline(n, target_seconds=15.0):
     threads = max(1, min(threads, 64))
     cells = n[0] * n[1] * n[2]
 
-    def timed(t):
-        t0 = time.perf_counter()
-        oracle.jacobi(n, t, seed=1, nthreads=threads)
-        return time.perf_counter() - t0
+    def rate(threads_, seconds):
+        def timed(t):
+            t0 = time.perf_counter()
+            oracle.jacobi(n, t, seed=1, nthreads=threads_)
+            return time.perf_counter() - t0
 
-    t1 = timed(1)
-    per = max((timed(3) - t1) / 2, 1e-4)
-    k = max(1, min(2000, int(target_seconds / per)))
-    tk = timed(1 + k)
-    dt = max(tk - t1, 1e-6)
-    return {"value": round(cells * k / dt / 1e9, 4), "unit": "GLUP/s", "cores": threads, "kind": "oracle",
+        t1 = timed(1)
+        per = max((timed(3) - t1) / 2, 1e-4)
+        k = max(1, min(2000, int(seconds / per)))
+        dt = max(timed(1 + k) - t1, 1e-6)
+        return cells * k / dt / 1e9, k, dt
+
+    value, k, dt = rate(threads, target_seconds)
+    one, k1, dt1 = rate(1, target_seconds / 3)
+    return {"value": round(value, 4), "unit": "GLUP/s", "cores": threads, "kind": "oracle",
             "sample": f"{n[0]}x{n[1]}x{n[2]} seeded grid (the benchmark's problem), {k} sweeps taking "
-                      f"{dt:.1f} s on {threads} threads, set-up and copy-out of a 1-sweep run subtracted"}
+                      f"{dt:.1f} s on {threads} threads, set-up and copy-out of a 1-sweep run subtracted",
+            "one_thread_value": round(one, 4), "one_thread_sample": f"{k1} sweeps taking {dt1:.1f} s",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def bench_overdecomposed(args):
@@ -159,6 +176,8 @@ def bench_overdecomposed(args):
     wall = time.perf_counter() - wall0
     ms_total = t_start.elapsed_time(t_end)
     ms_step = ms_total / args.steps
+    # each step's sweep time; a step also resets the interior and takes one checked sweep
+    ms_steps = [a.elapsed_time(b) for a, b in evs]
     kernel_ms = sum(a.elapsed_time(b) for a, b in evs) / (args.steps * (sweeps - 1))
     glups = cells * sweeps / (ms_step * 1e-3) / 1e9
     achieved = per_launch / (kernel_ms * 1e-3) / 1e9
@@ -181,12 +200,15 @@ def bench_overdecomposed(args):
                      "avg_launch_ms": round(kernel_ms, 4)},
         "residual": res,
         "wall_s": round(wall, 3),
+        "sweep_ms_per_step": {"mean": round(sum(ms_steps) / len(ms_steps), 3), "min": round(min(ms_steps), 3),
+                              "max": round(max(ms_steps), 3)},
     }
     s.close()
     del u0
     torch.cuda.empty_cache()
     if not args.no_copy:
         out["copy_GBps"] = round(copy_bandwidth(), 1)
+        out["roofline"]["frac_of_copy"] = round(achieved / out["copy_GBps"], 4)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
@@ -257,13 +279,50 @@ def bench_sweep(args):
         print(json.dumps({"metric": "streaming copy, 2 GiB", "copy_GBps": round(copy_bandwidth(), 1)}), flush=True)
 
 
+def bench_odf(args):
+    """Fusion strategies and graphs vs overdecomposition (the shape of Fig. 7 and 8 on one GPU).
+
+    A fixed grid is split into 1, 8, 64 and 512 blocks; every block runs its
+    own stream of GPU operations under no fusion, strategy A, B or C, each
+    launched directly or replayed from HIP graphs; the all-block fused sweep
+    is the reference.  Time per iteration shows where launches dominate."""
+    import torch
+    from paper_2202_11819_amd import api
+
+    edge = args.odf_edge
+    n = (edge,) * 3
+    cells = edge ** 3
+    modes = ["unfused_block", "block_a", "block_b", "block_c", "fused"]
+    for nb in (1, 2, 4, 8):
+        with api.Solver(n, nblk=(nb,) * 3, seed=1) as s:
+            for m in modes:
+                for cap in (False, True):
+                    mode = m + ("+graph" if cap else "")
+                    sweeps = args.odf_sweeps
+                    s.run(2, mode=mode)  # warm-up, captures the graphs
+                    torch.cuda.synchronize()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    w0 = time.perf_counter()
+                    e0.record()
+                    s.run(sweeps, mode=mode)
+                    e1.record()
+                    e1.synchronize()
+                    wall = time.perf_counter() - w0
+                    ms = e0.elapsed_time(e1) / sweeps
+                    print(json.dumps({"metric": "time per iteration vs overdecomposition", "grid": list(n),
+                                      "blocks": nb ** 3, "block_edge": edge // nb, "mode": mode,
+                                      "ms_per_iter": round(ms, 4), "host_ms_per_iter": round(1e3 * wall / sweeps, 4),
+                                      "GLUPs": round(cells / ms / 1e6, 2), "sweeps": sweeps}), flush=True)
+        torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="overdecomposed",
-                    choices=["overdecomposed", "modes", "sweep", "batch", "serve"])
+                    choices=["overdecomposed", "modes", "sweep", "batch", "serve", "odf"])
     ap.add_argument("--mode", default="graph", choices=["graph", "fused", "unfused_phase", "unfused_block"])
     ap.add_argument("--edge", type=int, default=512)
     ap.add_argument("--blocks", type=int, default=8)
@@ -279,6 +338,8 @@ def main():
     ap.add_argument("--load", type=float, default=0.8, help="serve workload: arrival rate / serial capacity")
     ap.add_argument("--fill-cells", type=int, default=-1, help="serve workload: pool round policy (-1: default)")
     ap.add_argument("--pool-tune", default="", help="serve workload: variant,zchunk of the pool's rounds")
+    ap.add_argument("--odf-edge", type=int, default=256, help="odf workload: grid edge")
+    ap.add_argument("--odf-sweeps", type=int, default=20, help="odf workload: timed sweeps per mode")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -298,6 +359,8 @@ def main():
     elif args.workload == "serve":
         from paper_2202_11819_amd import serve
         serve.bench_serve(args)
+    elif args.workload == "odf":
+        bench_odf(args)
 
 
 if __name__ == "__main__":

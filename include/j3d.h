@@ -73,12 +73,27 @@ typedef enum {
  *                 face values straight into the neighbours' halo storage of
  *                 the next iterate (strategy C, generalised to all blocks).
  *  GRAPH:         FUSED iterations captured once into a HIP graph holding an
- *                 even number of sweeps (both buffer parities), replayed.    */
+ *                 even number of sweeps (both buffer parities), replayed.
+ *  BLOCK_A/B/C:   the paper's fusion strategies at block granularity (one
+ *                 launch stream of operations per block, like UNFUSED_BLOCK):
+ *                 A fuses each block's six pack kernels into one; B also its
+ *                 six unpack kernels into one (pack, six copies, unpack,
+ *                 update); C runs one kernel per block that reads its halos
+ *                 where the neighbours keep them, updates, and hands its x
+ *                 faces over (no copies).
+ *  CAPTURED:      a flag OR-ed with any mode: its iterations are captured once
+ *                 into HIP graphs (50 sweeps per graph for FUSED, 2 for the
+ *                 others, whose graphs hold thousands of nodes) and replayed;
+ *                 GRAPH is FUSED | CAPTURED.  Results never depend on the mode. */
 typedef enum {
     J3D_UNFUSED_BLOCK = 0,
     J3D_UNFUSED_PHASE = 1,
     J3D_FUSED = 2,
-    J3D_GRAPH = 3
+    J3D_GRAPH = 3,
+    J3D_BLOCK_A = 4,
+    J3D_BLOCK_B = 5,
+    J3D_BLOCK_C = 6,
+    J3D_CAPTURED = 16
 } j3d_mode;
 
 /* One Jacobi3D problem.

@@ -185,13 +185,18 @@ struct j3d_solver {
     std::vector<int32_t> block_first;
     uint32_t persist_launches = 0;
     hipStream_t cap_stream = nullptr;
+    // Per-block modes: blocks' operations go round-robin to these streams, as
+    // each chare had its own stream, so independent blocks overlap on the GPU;
+    // phases are joined by events (fork/join on the caller's stream).
+    static constexpr int kSideStreams = 4;
+    hipStream_t side[kSideStreams] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[kSideStreams] = {};
     struct GraphEntry {
-        int parity, slot;
+        int mode, parity, slot;
         hipGraph_t graph;
         hipGraphExec_t exec;
     };
     std::vector<GraphEntry> graphs;
-    int graph_sweeps = 50;  // even: a replay returns to the same buffer parity
 };
 
 namespace {
@@ -257,17 +262,34 @@ j3d_status sweep(j3d_solver *s, int parity, bool fused, bool res, int32_t t0, in
     return hip_status(launch_sweep(s->tune.variant, a, grid, st), "sweep launch");
 }
 
-j3d_status direct_sweep(j3d_solver *s, int parity, bool fused, bool res, int32_t t0, int32_t cnt)
+// One workgroup per tile, whatever the tune's schedule (per-block launches).
+j3d_status sweep_tiles(j3d_solver *s, int parity, bool fused, bool res, int32_t t0, int32_t cnt, hipStream_t st)
 {
-    const int slot = (int)(s->persist_launches & 1);
-    if (s->tune.blocks_per_cu > 0) s->persist_launches++;
-    return sweep(s, parity, fused, res, t0, cnt, slot, s->stream);
+    SweepArgs a = base_args(s);
+    a.tile_begin = t0;
+    a.tile_count = cnt;
+    a.parity = parity;
+    a.flags = (fused ? SW_FUSED : 0) | (res ? SW_RES : 0);
+    return hip_status(launch_sweep(s->tune.variant, a, cnt, st), "sweep launch");
 }
 
-j3d_status get_graph(j3d_solver *s, int parity, int slot, hipGraphExec_t *out)
+// Sweeps per HIP graph: an even number, so a replay returns to the same
+// buffer parity.  A fused sweep is one node; the per-block modes put
+// thousands of nodes into one sweep, so their graphs hold two.
+int graph_sweeps(int mode) { return mode == J3D_FUSED ? 50 : 2; }
+
+// Modes whose sweep is one launch that may use the persistent schedule.
+bool persistent_mode(const j3d_solver *s, int mode)
+{
+    return s->tune.blocks_per_cu > 0 && (mode == J3D_FUSED || mode == J3D_UNFUSED_PHASE);
+}
+
+j3d_status one_sweep(j3d_solver *s, int mode, int p, bool res, int slot, hipStream_t st);
+
+j3d_status get_graph(j3d_solver *s, int mode, int parity, int slot, hipGraphExec_t *out)
 {
     for (auto &g : s->graphs)
-        if (g.parity == parity && g.slot == slot) {
+        if (g.mode == mode && g.parity == parity && g.slot == slot) {
             *out = g.exec;
             return J3D_OK;
         }
@@ -280,9 +302,9 @@ j3d_status get_graph(j3d_solver *s, int parity, int slot, hipGraphExec_t *out)
                                "begin capture");
     if (st != J3D_OK) return st;
     j3d_status launch_st = J3D_OK;
-    for (int i = 0; i < s->graph_sweeps && launch_st == J3D_OK; ++i) {
-        const int sl = s->tune.blocks_per_cu > 0 ? ((slot + i) & 1) : 0;
-        launch_st = sweep(s, parity ^ (i & 1), true, false, 0, s->ntiles, sl, s->cap_stream);
+    for (int i = 0; i < graph_sweeps(mode) && launch_st == J3D_OK; ++i) {
+        const int sl = persistent_mode(s, mode) ? ((slot + i) & 1) : 0;
+        launch_st = one_sweep(s, mode, parity ^ (i & 1), false, sl, s->cap_stream);
     }
     hipGraph_t graph = nullptr;
     st = hip_status(hipStreamEndCapture(s->cap_stream, &graph), "end capture");
@@ -297,62 +319,172 @@ j3d_status get_graph(j3d_solver *s, int parity, int slot, hipGraphExec_t *out)
         (void)hipGraphDestroy(graph);
         return st;
     }
-    s->graphs.push_back({parity, slot, graph, exec});
+    s->graphs.push_back({mode, parity, slot, graph, exec});
     *out = exec;
     return J3D_OK;
 }
 
-j3d_status run_unfused_block(j3d_solver *s, int p, bool res_last)
+j3d_status ensure_side_streams(j3d_solver *s)
+{
+    if (s->fork_ev) return J3D_OK;
+    for (int k = 0; k < j3d_solver::kSideStreams; ++k) {
+        j3d_status st = hip_status(hipStreamCreateWithFlags(&s->side[k], hipStreamNonBlocking), "side stream");
+        if (st == J3D_OK)
+            st = hip_status(hipEventCreateWithFlags(&s->join_ev[k], hipEventDisableTiming), "join event");
+        if (st != J3D_OK) return st;
+    }
+    return hip_status(hipEventCreateWithFlags(&s->fork_ev, hipEventDisableTiming), "fork event");
+}
+
+// The side streams start after everything enqueued on `main` so far.
+j3d_status fork_side(j3d_solver *s, hipStream_t main)
+{
+    j3d_status st = hip_status(hipEventRecord(s->fork_ev, main), "fork");
+    for (int k = 0; k < j3d_solver::kSideStreams && st == J3D_OK; ++k)
+        st = hip_status(hipStreamWaitEvent(s->side[k], s->fork_ev, 0), "fork");
+    return st;
+}
+
+// `main` continues after everything enqueued on the side streams so far.
+j3d_status join_side(j3d_solver *s, hipStream_t main)
+{
+    j3d_status st = J3D_OK;
+    for (int k = 0; k < j3d_solver::kSideStreams && st == J3D_OK; ++k) {
+        st = hip_status(hipEventRecord(s->join_ev[k], s->side[k]), "join");
+        if (st == J3D_OK) st = hip_status(hipStreamWaitEvent(main, s->join_ev[k], 0), "join");
+    }
+    return st;
+}
+
+// Per-block launch streams (the paper's per-chare GPU operations) under
+// fusion strategy `strat`: 0 none (six pack kernels, six copies, six unpack
+// kernels, one update per block), 1 = A (one pack kernel for the six faces),
+// 2 = B (A, and one unpack kernel), 3 = C (one kernel per block: halo reads,
+// update and x-face hand-off, no copies).
+j3d_status run_per_block(j3d_solver *s, int p, bool res_last, int strat, hipStream_t main)
 {
     const Plan &plan = s->plan;
+    const int32_t nb = (int32_t)plan.blocks.size();
+    j3d_status fst = ensure_side_streams(s);
+    if (fst == J3D_OK) fst = fork_side(s, main);
+    if (fst != J3D_OK) return fst;
+    auto lane = [&](int32_t b) { return s->side[b % j3d_solver::kSideStreams]; };
+    if (strat == 3) {
+        for (int32_t b = 0; b < nb; ++b) {
+            j3d_status st = sweep_tiles(s, p, true, res_last, s->block_first[b],
+                                        s->block_first[b + 1] - s->block_first[b], lane(b));
+            if (st != J3D_OK) return st;
+        }
+        return join_side(s, main);
+    }
     double *base = reinterpret_cast<double *>(s->arena);
     const BlockDesc *blocks = reinterpret_cast<const BlockDesc *>(s->arena + plan.off_blocks);
-    const int32_t nb = (int32_t)plan.blocks.size();
+    auto faces = [](const BlockDesc &B, int64_t fsz[6]) {
+        const int64_t ex = B.ext[0], ey = B.ext[1], ez = B.ext[2];
+        fsz[0] = fsz[1] = ey * ez;
+        fsz[2] = fsz[3] = ex * ez;
+        fsz[4] = fsz[5] = ex * ey;
+    };
     // every block packs and sends its faces ...
     for (int32_t b = 0; b < nb; ++b) {
         const BlockDesc &B = plan.blocks[b];
-        const int64_t ex = B.ext[0], ey = B.ext[1], ez = B.ext[2];
-        const int64_t fsz[6] = {ey * ez, ey * ez, ex * ez, ex * ez, ex * ey, ex * ey};
-        int64_t fo[6];
+        hipStream_t stream = lane(b);
+        int64_t fsz[6], fo[6];
+        faces(B, fsz);
         fo[0] = 0;
         for (int f = 1; f < 6; ++f) fo[f] = fo[f - 1] + fsz[f - 1];
-        for (int f = 0; f < 6; ++f) {
-            if (B.nbr[f] < 0) continue;
-            j3d_status st = hip_status(launch_pack(base, blocks, b, 1, (int32_t)fsz[f], p, 1 << f, s->stream),
+        int mask = 0;
+        int64_t maxf = 0;
+        for (int f = 0; f < 6; ++f)
+            if (B.nbr[f] >= 0) {
+                mask |= 1 << f;
+                maxf = std::max(maxf, fsz[f]);
+            }
+        if (strat == 0) {
+            for (int f = 0; f < 6; ++f) {
+                if (B.nbr[f] < 0) continue;
+                j3d_status st = hip_status(launch_pack(base, blocks, b, 1, (int32_t)fsz[f], p, 1 << f, stream),
+                                           "pack launch");
+                if (st != J3D_OK) return st;
+            }
+        } else if (mask) {
+            j3d_status st = hip_status(launch_pack(base, blocks, b, 1, (int32_t)maxf, p, mask, stream),
                                        "pack launch");
             if (st != J3D_OK) return st;
         }
         for (int f = 0; f < 6; ++f) {
             if (B.nbr[f] < 0) continue;
             const BlockDesc &N = plan.blocks[B.nbr[f]];
-            const int64_t nex = N.ext[0], ney = N.ext[1], nez = N.ext[2];
-            const int64_t nsz[6] = {ney * nez, ney * nez, nex * nez, nex * nez, nex * ney, nex * ney};
+            int64_t nsz[6];
+            faces(N, nsz);
             int64_t no = 0;
             for (int g = 0; g < (f ^ 1); ++g) no += nsz[g];
             double *dst = base + N.sr_off + N.face_total + no;
             const double *src = base + B.sr_off + fo[f];
             j3d_status st = hip_status(hipMemcpyAsync(dst, src, (size_t)fsz[f] * sizeof(double),
-                                                      hipMemcpyDeviceToDevice, s->stream),
+                                                      hipMemcpyDeviceToDevice, stream),
                                        "halo copy");
             if (st != J3D_OK) return st;
         }
     }
-    // ... then every block unpacks what it received and updates.
+    // ... then, once every face has arrived, every block unpacks what it
+    // received and updates.
+    j3d_status jst = join_side(s, main);
+    if (jst == J3D_OK) jst = fork_side(s, main);
+    if (jst != J3D_OK) return jst;
     for (int32_t b = 0; b < nb; ++b) {
         const BlockDesc &B = plan.blocks[b];
-        const int64_t ex = B.ext[0], ey = B.ext[1], ez = B.ext[2];
-        const int64_t fsz[6] = {ey * ez, ey * ez, ex * ez, ex * ez, ex * ey, ex * ey};
-        for (int f = 0; f < 6; ++f) {
-            if (B.nbr[f] < 0) continue;
-            j3d_status st = hip_status(
-                launch_unpack(base, blocks, b, 1, (int32_t)fsz[f], p, 1 << f, s->stream), "unpack launch");
-            if (st != J3D_OK) return st;
+        hipStream_t stream = lane(b);
+        int64_t fsz[6];
+        faces(B, fsz);
+        int mask = 0;
+        int64_t maxf = 0;
+        for (int f = 0; f < 6; ++f)
+            if (B.nbr[f] >= 0) {
+                mask |= 1 << f;
+                maxf = std::max(maxf, fsz[f]);
+            }
+        if (strat == 2) {
+            if (mask) {
+                j3d_status st = hip_status(launch_unpack(base, blocks, b, 1, (int32_t)maxf, p, mask, stream),
+                                           "unpack launch");
+                if (st != J3D_OK) return st;
+            }
+        } else {
+            for (int f = 0; f < 6; ++f) {
+                if (B.nbr[f] < 0) continue;
+                j3d_status st = hip_status(launch_unpack(base, blocks, b, 1, (int32_t)fsz[f], p, 1 << f, stream),
+                                           "unpack launch");
+                if (st != J3D_OK) return st;
+            }
         }
-        j3d_status st = direct_sweep(s, p, false, res_last, s->block_first[b],
-                                     s->block_first[b + 1] - s->block_first[b]);
+        j3d_status st = sweep_tiles(s, p, false, res_last, s->block_first[b],
+                                    s->block_first[b + 1] - s->block_first[b], stream);
         if (st != J3D_OK) return st;
     }
-    return J3D_OK;
+    return join_side(s, main);
+}
+
+// One sweep of `mode` reading parity p, enqueued on st.
+j3d_status one_sweep(j3d_solver *s, int mode, int p, bool res, int slot, hipStream_t st)
+{
+    switch (mode) {
+    case J3D_FUSED:
+        return sweep(s, p, true, res, 0, s->ntiles, slot, st);
+    case J3D_UNFUSED_PHASE: {
+        j3d_status r = refresh_halos(s->plan, s->arena, 0, (int32_t)s->plan.blocks.size(), p, st);
+        return r != J3D_OK ? r : sweep(s, p, false, res, 0, s->ntiles, slot, st);
+    }
+    case J3D_UNFUSED_BLOCK:
+        return run_per_block(s, p, res, 0, st);
+    case J3D_BLOCK_A:
+        return run_per_block(s, p, res, 1, st);
+    case J3D_BLOCK_B:
+        return run_per_block(s, p, res, 2, st);
+    case J3D_BLOCK_C:
+        return run_per_block(s, p, res, 3, st);
+    }
+    return set_error(J3D_EINVAL, "unknown mode %d", mode);
 }
 
 }  // namespace
@@ -463,11 +595,18 @@ j3d_status j3d_get_tune(const j3d_solver *s, j3d_tune *out)
     return J3D_OK;
 }
 
-j3d_status j3d_run(j3d_solver *s, int64_t iters, j3d_mode mode, double *residual_out)
+j3d_status j3d_run(j3d_solver *s, int64_t iters, j3d_mode mode_in, double *residual_out)
 {
     if (!s) return set_error(J3D_EINVAL, "solver is NULL");
     if (iters < 0) return set_error(J3D_EINVAL, "iters %lld < 0", (long long)iters);
-    if (mode < J3D_UNFUSED_BLOCK || mode > J3D_GRAPH) return set_error(J3D_EINVAL, "unknown mode %d", (int)mode);
+    int mode = (int)mode_in;
+    bool captured = (mode & J3D_CAPTURED) != 0;
+    mode &= ~(int)J3D_CAPTURED;
+    if (mode == J3D_GRAPH) {
+        mode = J3D_FUSED;
+        captured = true;
+    }
+    if (mode < J3D_UNFUSED_BLOCK || mode > J3D_BLOCK_C) return set_error(J3D_EINVAL, "unknown mode %d", (int)mode_in);
     if (iters == 0) {
         if (residual_out) *residual_out = 0.0;
         return J3D_OK;
@@ -475,7 +614,8 @@ j3d_status j3d_run(j3d_solver *s, int64_t iters, j3d_mode mode, double *residual
     const bool want_res = residual_out != nullptr;
     unsigned long long *res = reinterpret_cast<unsigned long long *>(s->arena + s->plan.off_res);
     j3d_status st = J3D_OK;
-    const bool fused = mode == J3D_FUSED || mode == J3D_GRAPH;
+    // modes that read x halos where the previous fused sweep handed them over
+    const bool fused = mode == J3D_FUSED || mode == J3D_BLOCK_C;
     if (fused && !s->ghosts_fresh) {
         st = refresh_halos(s->plan, s->arena, 0, (int32_t)s->plan.blocks.size(), s->parity, s->stream);
         if (st != J3D_OK) return st;
@@ -485,44 +625,27 @@ j3d_status j3d_run(j3d_solver *s, int64_t iters, j3d_mode mode, double *residual
         st = hip_status(launch_fill_u64(res, 1, 0ull, s->stream), "residual reset");
         if (st != J3D_OK) return st;
     }
+    const bool persist = persistent_mode(s, mode);
     int p = s->parity;
     int64_t done = 0;
-    if (mode == J3D_GRAPH) {
+    if (captured) {
+        const int gs = graph_sweeps(mode);
         const int64_t plain = iters - (want_res ? 1 : 0);
-        const int64_t reps = plain / s->graph_sweeps;
-        for (int64_t r = 0; r < reps; ++r) {
-            const int slot = s->tune.blocks_per_cu > 0 ? (int)(s->persist_launches & 1) : 0;
+        for (int64_t r = 0; r < plain / gs; ++r) {
+            const int slot = persist ? (int)(s->persist_launches & 1) : 0;
             hipGraphExec_t exec = nullptr;
-            st = get_graph(s, p, slot, &exec);
+            st = get_graph(s, mode, p, slot, &exec);
             if (st != J3D_OK) return st;
             st = hip_status(hipGraphLaunch(exec, s->stream), "graph launch");
             if (st != J3D_OK) return st;
-            if (s->tune.blocks_per_cu > 0) s->persist_launches += (uint32_t)s->graph_sweeps;
-            done += s->graph_sweeps;
+            if (persist) s->persist_launches += (uint32_t)gs;
+            done += gs;
         }
     }
     for (; done < iters; ++done) {
-        const bool last = done + 1 == iters;
-        const bool res_here = want_res && last;
-        switch (mode) {
-        case J3D_FUSED:
-        case J3D_GRAPH:
-            st = direct_sweep(s, p, true, res_here, 0, s->ntiles);
-            break;
-        case J3D_UNFUSED_PHASE: {
-            double *base = reinterpret_cast<double *>(s->arena);
-            const BlockDesc *blocks = reinterpret_cast<const BlockDesc *>(s->arena + s->plan.off_blocks);
-            const int32_t nb = (int32_t)s->plan.blocks.size();
-            st = refresh_halos(s->plan, s->arena, 0, nb, p, s->stream);
-            (void)base;
-            (void)blocks;
-            if (st == J3D_OK) st = direct_sweep(s, p, false, res_here, 0, s->ntiles);
-            break;
-        }
-        case J3D_UNFUSED_BLOCK:
-            st = run_unfused_block(s, p, res_here);
-            break;
-        }
+        const bool res_here = want_res && done + 1 == iters;
+        const int slot = persist ? (int)(s->persist_launches++ & 1) : 0;
+        st = one_sweep(s, mode, p, res_here, slot, s->stream);
         if (st != J3D_OK) return st;
         p ^= 1;
     }
@@ -560,8 +683,15 @@ j3d_status j3d_destroy(j3d_solver *s)
 {
     if (!s) return set_error(J3D_EINVAL, "solver is NULL");
     j3d_status st = hip_status(hipStreamSynchronize(s->stream), "destroy");
+    for (hipStream_t x : s->side)
+        if (x) (void)hipStreamSynchronize(x);
     drop_graphs(s);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    for (int k = 0; k < j3d_solver::kSideStreams; ++k) {
+        if (s->side[k]) (void)hipStreamDestroy(s->side[k]);
+        if (s->join_ev[k]) (void)hipEventDestroy(s->join_ev[k]);
+    }
+    if (s->fork_ev) (void)hipEventDestroy(s->fork_ev);
     delete s;
     return st;
 }

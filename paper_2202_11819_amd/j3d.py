@@ -50,7 +50,18 @@ J3D_OK, J3D_EINVAL, J3D_ENOMEM, J3D_EBUDGET, J3D_EBUSY, J3D_EDEVICE, J3D_ESTATE 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EBUDGET", -4: "EBUSY", -5: "EDEVICE", -6: "ESTATE"}
 
 J3D_UNFUSED_BLOCK, J3D_UNFUSED_PHASE, J3D_FUSED, J3D_GRAPH = 0, 1, 2, 3
-MODES = {"unfused_block": 0, "unfused_phase": 1, "fused": 2, "graph": 3}
+MODES = {"unfused_block": 0, "unfused_phase": 1, "fused": 2, "graph": 3, "block_a": 4, "block_b": 5,
+         "block_c": 6}
+J3D_CAPTURED = 16
+
+
+def mode_value(mode) -> int:
+    """j3d_mode value of a mode name; "<name>+graph" captures it in HIP graphs."""
+    if not isinstance(mode, str):
+        return int(mode)
+    if mode.endswith("+graph"):
+        return MODES[mode[: -len("+graph")]] | J3D_CAPTURED
+    return MODES[mode]
 
 
 class J3DError(RuntimeError):
@@ -244,7 +255,7 @@ def j3d_get_tune(h):
 
 
 def j3d_run(h, iters: int, mode, want_residual: bool = False):
-    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    m = mode_value(mode)
     if want_residual:
         r = c_double()
         _check(_lib.j3d_run(h, int(iters), m, byref(r)), "j3d_run")

@@ -221,3 +221,43 @@ def test_pool_zero_iterations_returns_initial_grid(env):
         u, r, it = pool.result(slot)
         assert it == 0 and r == 0.0
         assert np.array_equal(u, oracle.init_interior((17, 9, 5), 3, 2))
+
+
+# ---- the batched and served workloads at their own sizes -----------------------
+
+@pytest.mark.slow
+def test_batch_full_workload_matches_oracle(env):
+    # all 256 problems of the batched benchmark (sizes 32..256 per axis,
+    # 100..1000 sweeps), default tile, against the oracle problem by problem
+    oracle, api, j3d, W = env
+    specs = W.batch()
+    with api.Batch([_problem(api, s) for s in specs], [s.iters for s in specs]) as b:
+        res = b.run()
+        for i, s in enumerate(specs):
+            want, want_r, _ = oracle.jacobi(s.n, s.iters, bc=s.bc, seed=s.seed, pid=s.pid, nthreads=NTH)
+            assert res[i] == want_r, i
+            assert np.array_equal(b.get_interior(i), want), i
+
+
+@pytest.mark.slow
+def test_pool_served_sizes_sample_matches_oracle(env):
+    # a seeded sample of 32 requests of the served benchmark's mix (32..384
+    # per axis, 50..2000 sweeps, residual every 50) plus its smallest and its
+    # largest request, all admitted together, against the oracle's checked run
+    oracle, api, j3d, W = env
+    from paper_2202_11819_amd import serve
+    trace = W.serve_trace(count=1100, rate=1.0)
+    rng = np.random.default_rng(11)
+    pick = sorted(set(rng.choice(len(trace), 32, replace=False).tolist()))
+    cells = [int(np.prod(r.spec.n)) for r in trace]
+    pick += [int(np.argmin(cells)), int(np.argmax(cells))]
+    reqs = [W.Request(arrival=0.0, spec=trace[i].spec) for i in pick]
+    recs, _ = serve.serve_pool(reqs, budget_bytes=40 << 30, max_slots=64, keep_results=True)
+    for rec, req in zip(recs, reqs):
+        s = req.spec
+        want, want_r, done = oracle.jacobi(s.n, s.iters, bc=s.bc, seed=s.seed, pid=s.pid, check_every=50,
+                                           nthreads=NTH)
+        assert rec["iters"] == done == s.iters
+        assert rec["residual"] == want_r, s.n
+        assert np.array_equal(rec["u"], want), s.n
+

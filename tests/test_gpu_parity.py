@@ -14,7 +14,8 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 NTH = min(16, os.cpu_count() or 1)
-MODES = ("graph", "fused", "unfused_phase", "unfused_block")
+MODES = ("graph", "fused", "unfused_phase", "unfused_block", "block_a", "block_b", "block_c",
+         "unfused_block+graph", "block_a+graph", "block_b+graph", "block_c+graph", "unfused_phase+graph")
 
 
 @pytest.fixture(scope="module")
@@ -172,7 +173,9 @@ def test_resume_and_mode_switch(env):
     with api.Solver(n, nblk=nblk, bc=bc, seed=2) as s:
         s.run(7, mode="unfused_block")
         s.run(5, mode="graph")
-        s.run(11, mode="unfused_phase")
+        s.run(3, mode="block_c+graph")
+        s.run(3, mode="block_a")
+        s.run(5, mode="unfused_phase")
         r = s.run(7, mode="fused", residual=True)
         assert s.iters_done() == 30
         assert np.array_equal(s.get_interior(), want) and r == want_r
@@ -220,6 +223,10 @@ def test_errors_leave_state_untouched(env):
             j3d.j3d_set_tune(s.h, 999, 0, 0)
         with pytest.raises(j3d.J3DError):
             j3d.j3d_set_face(s.h, 6, 0, False)
+        for bad_mode in (7, 8, 15, 3 | 16 | 32, -1):
+            with pytest.raises(j3d.J3DError) as e:
+                s.run(2, mode=bad_mode)
+            assert e.value.status == j3d.J3D_EINVAL
         s.run(5, mode="graph")
         want, _, _ = oracle.jacobi((16, 16, 16), 5, seed=3)
         assert np.array_equal(s.get_interior(), want)
@@ -256,6 +263,22 @@ def test_overdecomposed_512_full_run_equals_single_block(env):
     assert r8 == r1
     assert bool((u8 == u1).all())
     assert 0.0 < r8 < 1e-2
+
+
+@pytest.mark.slow
+def test_overdecomposed_512_full_run_matches_oracle(env):
+    # The benchmark's whole step: 512^3 as 8^3 blocks, 1000 sweeps in graph
+    # mode with the last sweep's residual, against the oracle's full run on the
+    # host cores (about 15 s on 16 threads).
+    oracle, api, _ = env
+    n = (512, 512, 512)
+    with api.Solver(n, nblk=(8, 8, 8), seed=1) as s:
+        r = s.run(1000, mode="graph", residual=True)
+        got = s.get_interior()
+    say("oracle: 512^3 x 1000 sweeps")
+    want, want_r, done = oracle.jacobi(n, 1000, seed=1, nthreads=NTH)
+    assert done == 1000 and r == want_r
+    assert np.array_equal(got, want), f"max |diff| {np.abs(got - want).max()}"
 
 
 def test_overdecomposed_512_eigenmode_bound(env):
