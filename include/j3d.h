@@ -68,10 +68,11 @@ typedef enum {
  *                 thread per cell of the largest face, each thread visiting
  *                 the six faces), one exchange copy kernel, one fused unpack
  *                 kernel (strategy B) and one update kernel, all blocks at once.
- *  FUSED:         per iteration one kernel for all blocks that reads its halos
- *                 where the neighbours left them, updates, and writes its new
- *                 face values straight into the neighbours' halo storage of
- *                 the next iterate (strategy C, generalised to all blocks).
+ *  FUSED:         per iteration one kernel for all blocks (strategy C,
+ *                 generalised to all blocks): it reads its y and z halos
+ *                 straight from the neighbours' current iterate, updates, and
+ *                 hands its new x faces to the neighbours' x-halo storage of
+ *                 the next iterate; pack, exchange and unpack need no copy.
  *  GRAPH:         FUSED iterations captured once into a HIP graph holding an
  *                 even number of sweeps (both buffer parities), replayed.
  *  BLOCK_A/B/C:   the paper's fusion strategies at block granularity (one

@@ -7,12 +7,14 @@
 // marches along z; every cell is read from HBM once (x-contiguous rows, whole
 // 64-lane waves per row segment) and written once; the four in-plane
 // neighbours come from a double-buffered LDS copy of the current plane with a
-// one-cell ring, the two z-neighbours from registers.  Halo values are read
-// where the neighbour block wrote them, and a cell on a block face writes its
-// new value straight into the neighbour's halo storage of the next iterate
-// (pack, exchange and unpack as a single store).  The other kernels here are
-// the unfused pack / exchange / unpack of Fig. 1 and Fig. 3, the seeded
-// initialisation, and dense <-> block copies.
+// one-cell ring, the two z-neighbours from registers.  In the fused sweep the
+// y and z halos are read straight from the neighbour blocks' current iterate
+// (pack, exchange and unpack become one read across the block boundary), and
+// a block's x faces, which a neighbour could only read one double per row,
+// are handed to the neighbour's x-halo array of the next iterate as two
+// coalesced stores per plane.  The other kernels here are the unfused pack /
+// exchange / unpack of Fig. 1 and Fig. 3, the seeded initialisation, and
+// dense <-> block copies.
 //
 // Arithmetic of the update, fixed for bit-exact results: the 7-term sum in the
 // order centre, x-, x+, y-, y+, z-, z+, each addition rounded, then one
