@@ -216,7 +216,8 @@ def bench_overdecomposed(args):
 
 
 def bench_modes(args):
-    """The same grid in every mode (unfused per block, unfused per phase, fused, graph)."""
+    """The same grid in every mode: per-block streams under each fusion strategy, the
+    host-staged exchange with and without overlap, per-phase, fused and graph."""
     import torch
     from paper_2202_11819_amd import api
     from paper_2202_11819_amd import workloads as W
@@ -224,10 +225,9 @@ def bench_modes(args):
     spec = W.overdecomposed(nb=args.blocks, edge=args.edge, iters=args.sweeps)
     n = spec.n
     cells = n[0] * n[1] * n[2]
-    s = api.Solver(n, nblk=spec.nblk, seed=spec.seed)
-    ref = None
-    for mode, iters in [("unfused_block", 10), ("unfused_phase", 100), ("fused", args.sweeps),
-                        ("graph", args.sweeps)]:
+    for mode, iters in [("unfused_block", 10), ("unfused_block+graph", 10), ("block_a", 10), ("block_b", 10),
+                        ("block_c", 20), ("block_c+graph", 20), ("host_staged", 10), ("host_overlap", 10),
+                        ("unfused_phase", 100), ("fused", args.sweeps), ("graph", args.sweeps)]:
         s2 = api.Solver(n, nblk=spec.nblk, seed=spec.seed)
         s2.run(2, mode=mode)
         torch.cuda.synchronize()
@@ -243,7 +243,6 @@ def bench_modes(args):
         print(json.dumps(out), flush=True)
         s2.close()
         torch.cuda.empty_cache()
-    s.close()
 
 
 def bench_sweep(args):
@@ -292,7 +291,7 @@ def bench_odf(args):
     edge = args.odf_edge
     n = (edge,) * 3
     cells = edge ** 3
-    modes = ["unfused_block", "block_a", "block_b", "block_c", "fused"]
+    modes = ["unfused_block", "block_a", "block_b", "block_c", "host_staged", "host_overlap", "fused"]
     for nb in (1, 2, 4, 8):
         with api.Solver(n, nblk=(nb,) * 3, seed=1) as s:
             for m in modes:
@@ -316,13 +315,37 @@ def bench_odf(args):
         torch.cuda.empty_cache()
 
 
+def bench_hostex(args):
+    """Host-staged exchange with and without overlap (Fig. 1's computation-communication
+    overlap) on 1024^3 at 2^3 and 4^3 blocks, beside the fused device-resident sweep."""
+    import torch
+    from paper_2202_11819_amd import api
+
+    n = (1024,) * 3
+    for nb in (2, 4):
+        with api.Solver(n, nblk=(nb,) * 3, seed=1) as s:
+            for mode in ("fused", "host_staged", "host_overlap", "host_staged+graph", "host_overlap+graph"):
+                s.run(2, mode=mode)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                s.run(args.odf_sweeps, mode=mode)
+                e1.record()
+                e1.synchronize()
+                ms = e0.elapsed_time(e1) / args.odf_sweeps
+                print(json.dumps({"metric": "time per iteration, host-staged exchange", "grid": list(n),
+                                  "blocks": nb ** 3, "mode": mode, "ms_per_iter": round(ms, 4),
+                                  "GLUPs": round(1024 ** 3 / ms / 1e6, 2), "sweeps": args.odf_sweeps}), flush=True)
+        torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="overdecomposed",
-                    choices=["overdecomposed", "modes", "sweep", "batch", "serve", "odf"])
+                    choices=["overdecomposed", "modes", "sweep", "batch", "serve", "odf", "hostex"])
     ap.add_argument("--mode", default="graph", choices=["graph", "fused", "unfused_phase", "unfused_block"])
     ap.add_argument("--edge", type=int, default=512)
     ap.add_argument("--blocks", type=int, default=8)
@@ -361,6 +384,8 @@ def main():
         serve.bench_serve(args)
     elif args.workload == "odf":
         bench_odf(args)
+    elif args.workload == "hostex":
+        bench_hostex(args)
 
 
 if __name__ == "__main__":

@@ -82,6 +82,15 @@ typedef enum {
  *                 update); C runs one kernel per block that reads its halos
  *                 where the neighbours keep them, updates, and hands its x
  *                 faces over (no copies).
+ *  HOST_STAGED:   the exchange staged through host memory, as without
+ *                 GPU-aware communication: one pack kernel for all blocks,
+ *                 every face copied to page-locked host memory (into the
+ *                 receiver's slot), each block's received faces copied back,
+ *                 then unpack and update.
+ *  HOST_OVERLAP:  HOST_STAGED with the update running on a second stream while
+ *                 the faces are in transit (Fig. 1's overlap of computation
+ *                 and communication); the cells that read a halo are then
+ *                 recomputed from the delivered halos.
  *  CAPTURED:      a flag OR-ed with any mode: its iterations are captured once
  *                 into HIP graphs (50 sweeps per graph for FUSED, 2 for the
  *                 others, whose graphs hold thousands of nodes) and replayed;
@@ -94,6 +103,8 @@ typedef enum {
     J3D_BLOCK_A = 4,
     J3D_BLOCK_B = 5,
     J3D_BLOCK_C = 6,
+    J3D_HOST_STAGED = 7,
+    J3D_HOST_OVERLAP = 8,
     J3D_CAPTURED = 16
 } j3d_mode;
 

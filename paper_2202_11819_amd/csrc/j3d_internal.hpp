@@ -142,6 +142,10 @@ int launch_init(double *base, const BlockDesc *blocks, int32_t block_begin, int3
 // Pack (faces in `face_mask`) of parity `parity` into send buffers.
 int launch_pack(double *base, const BlockDesc *blocks, int32_t block_begin, int32_t nblocks,
                 int32_t max_face, int parity, int face_mask, void *stream);
+// Recompute the outer one-cell shell of each block (parity -> parity^1) from the
+// current halo storage; max_shell bounds the shell cells of any block.
+int launch_shell(double *base, const BlockDesc *blocks, int32_t block_begin, int32_t nblocks, int64_t max_shell,
+                 int parity, void *stream);
 // Exchange S[b][f] -> R[nbr][opp f] for all blocks in the range.
 int launch_exchange(double *base, const BlockDesc *blocks, int32_t block_begin, int32_t nblocks,
                     int32_t max_face, void *stream);

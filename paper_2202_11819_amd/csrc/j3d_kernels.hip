@@ -692,6 +692,73 @@ __global__ __launch_bounds__(256) void unpack_kernel(double *base, const BlockDe
     }
 }
 
+// ---- block shell update -------------------------------------------------------
+//
+// The cells of a block that read a halo (its outer one-cell shell) updated from
+// the current halo storage, with the same expression and order as the sweep.
+// Used after an update that ran while the halos were still in transit: the
+// interior cells were already right, the shell cells are recomputed.
+
+__device__ __forceinline__ int64_t shell_cells(int ex, int ey, int ez)
+{
+    const int64_t plane = (int64_t)ex * ey;
+    const int64_t ring = (ex <= 2 || ey <= 2) ? plane : 2 * (int64_t)ex + 2 * (int64_t)(ey - 2);
+    return (ez >= 2 ? 2 : 1) * plane + (int64_t)(ez > 2 ? ez - 2 : 0) * ring;
+}
+
+__global__ __launch_bounds__(256) void shell_kernel(double *base, const BlockDesc *blocks, int block_begin,
+                                                    int nblocks, int parity)
+{
+    for (int bb = blockIdx.y; bb < nblocks; bb += gridDim.y) {
+        const BlockDesc &B = blocks[block_begin + bb];
+        const int ex = B.ext[0], ey = B.ext[1], ez = B.ext[2], pitch = B.pitch;
+        const int64_t n = shell_cells(ex, ey, ez);
+        const int64_t plane = (int64_t)ex * ey;
+        const int64_t full = (ez >= 2 ? 2 : 1) * plane;
+        const int64_t ring = (ex <= 2 || ey <= 2) ? plane : 2 * (int64_t)ex + 2 * (int64_t)(ey - 2);
+        const int64_t ps = (int64_t)(ey + 2) * pitch;
+        const double *cur = base + B.off[parity];
+        double *nxt = base + B.off[parity ^ 1];
+        const double *X = base + B.xoff[parity];
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+            int x, y, z;
+            if (i < full) {
+                z = i < plane ? 0 : ez - 1;
+                const int64_t r = i % plane;
+                x = (int)(r % ex);
+                y = (int)(r / ex);
+            } else {
+                const int64_t j = i - full, r = j % ring;
+                z = 1 + (int)(j / ring);
+                if (ex <= 2 || ey <= 2) {
+                    x = (int)(r % ex);
+                    y = (int)(r / ex);
+                } else if (r < ex) {
+                    x = (int)r;
+                    y = 0;
+                } else if (r < 2 * (int64_t)ex) {
+                    x = (int)(r - ex);
+                    y = ey - 1;
+                } else {
+                    const int64_t q = r - 2 * (int64_t)ex;
+                    y = 1 + (int)(q / 2);
+                    x = (q & 1) ? ex - 1 : 0;
+                }
+            }
+            const int64_t c = (int64_t)(z + 1) * ps + (int64_t)(y + 1) * pitch + x;
+            double s = cur[c];
+            s += x > 0 ? cur[c - 1] : X[(int64_t)z * ey + y];
+            s += x < ex - 1 ? cur[c + 1] : X[(int64_t)ey * ez + (int64_t)z * ey + y];
+            s += cur[c - pitch];
+            s += cur[c + pitch];
+            s += cur[c - ps];
+            s += cur[c + ps];
+            nxt[c] = s * kW;
+        }
+    }
+}
+
 // ---- initialisation and dense <-> block copies -----------------------------
 
 __global__ __launch_bounds__(256) void init_kernel(double *base, const BlockDesc *blocks,
@@ -1020,6 +1087,15 @@ int launch_unpack(double *base, const BlockDesc *blocks, int32_t block_begin, in
     const dim3 grid(grid_for(max_face, 256, 1 << 30), nblocks < kMaxGridY ? nblocks : kMaxGridY);
     hipLaunchKernelGGL(unpack_kernel, grid, dim3(256), 0, (hipStream_t)stream, base, blocks,
                        block_begin, nblocks, parity, face_mask);
+    return (int)hipGetLastError();
+}
+
+int launch_shell(double *base, const BlockDesc *blocks, int32_t block_begin, int32_t nblocks, int64_t max_shell,
+                 int parity, void *stream)
+{
+    const dim3 grid(grid_for(max_shell, 256, 4096), nblocks < kMaxGridY ? nblocks : kMaxGridY);
+    hipLaunchKernelGGL(shell_kernel, grid, dim3(256), 0, (hipStream_t)stream, base, blocks, block_begin, nblocks,
+                       parity);
     return (int)hipGetLastError();
 }
 

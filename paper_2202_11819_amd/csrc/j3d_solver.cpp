@@ -8,6 +8,8 @@
 // device never synchronise inside the iteration loop (Sec. III-C removes such
 // synchronisations); only a requested residual or a host copy waits.
 #include <algorithm>
+#include <climits>
+#include <cstdint>
 #include <cstring>
 #include <new>
 
@@ -191,6 +193,10 @@ struct j3d_solver {
     static constexpr int kSideStreams = 4;
     hipStream_t side[kSideStreams] = {};
     hipEvent_t fork_ev = nullptr, join_ev[kSideStreams] = {};
+    // Host-staged modes: page-locked mirror of the send/receive region.
+    double *host_sr = nullptr;
+    int64_t sr_lo = 0, sr_hi = 0;  // doubles from the arena base
+    int64_t max_shell = 0;
     struct GraphEntry {
         int mode, parity, slot;
         hipGraph_t graph;
@@ -465,6 +471,87 @@ j3d_status run_per_block(j3d_solver *s, int p, bool res_last, int strat, hipStre
     return join_side(s, main);
 }
 
+j3d_status ensure_host_mirror(j3d_solver *s)
+{
+    if (s->host_sr) return J3D_OK;
+    int64_t lo = INT64_MAX, hi = 0, shell = 0;
+    for (const BlockDesc &B : s->plan.blocks) {
+        lo = std::min<int64_t>(lo, B.sr_off);
+        hi = std::max<int64_t>(hi, B.sr_off + 2 * B.face_total);
+        const int64_t ex = B.ext[0], ey = B.ext[1], ez = B.ext[2];
+        const int64_t plane = ex * ey, ring = (ex <= 2 || ey <= 2) ? plane : 2 * ex + 2 * (ey - 2);
+        shell = std::max(shell, (ez >= 2 ? 2 : 1) * plane + std::max<int64_t>(ez - 2, 0) * ring);
+    }
+    j3d_status st = hip_status(hipHostMalloc((void **)&s->host_sr, (size_t)(hi - lo) * sizeof(double), 0),
+                               "page-locked staging buffer");
+    if (st != J3D_OK) {
+        s->host_sr = nullptr;
+        return st;
+    }
+    s->sr_lo = lo;
+    s->sr_hi = hi;
+    s->max_shell = shell;
+    return J3D_OK;
+}
+
+// One iteration with the exchange staged through host memory.  overlap: the
+// update runs on a side stream while the faces travel, and the shell cells
+// (the ones that read a halo) are recomputed once the halos are unpacked.
+j3d_status run_host_staged(j3d_solver *s, int p, bool res, bool overlap, hipStream_t main)
+{
+    const Plan &plan = s->plan;
+    const int32_t nb = (int32_t)plan.blocks.size();
+    double *base = reinterpret_cast<double *>(s->arena);
+    const BlockDesc *blocks = reinterpret_cast<const BlockDesc *>(s->arena + plan.off_blocks);
+    double *H = s->host_sr - s->sr_lo;  // indexed like the arena, over the send/receive region only
+    j3d_status st = J3D_OK;
+    if (overlap) {
+        st = ensure_side_streams(s);
+        if (st == J3D_OK) st = fork_side(s, main);
+        if (st == J3D_OK) st = sweep_tiles(s, p, false, false, 0, s->ntiles, s->side[0]);
+        if (st != J3D_OK) return st;
+    }
+    st = hip_status(launch_pack(base, blocks, 0, nb, plan.max_face, p, 0x3f, main), "pack launch");
+    if (st != J3D_OK) return st;
+    // every face to host memory, into the receiver's slot ...
+    for (int32_t b = 0; b < nb; ++b) {
+        const BlockDesc &B = plan.blocks[b];
+        const int64_t fsz[6] = {(int64_t)B.ext[1] * B.ext[2], (int64_t)B.ext[1] * B.ext[2],
+                                (int64_t)B.ext[0] * B.ext[2], (int64_t)B.ext[0] * B.ext[2],
+                                (int64_t)B.ext[0] * B.ext[1], (int64_t)B.ext[0] * B.ext[1]};
+        int64_t fo = 0;
+        for (int f = 0; f < 6; fo += fsz[f], ++f) {
+            if (B.nbr[f] < 0) continue;
+            const BlockDesc &N = plan.blocks[B.nbr[f]];
+            const int64_t nsz[6] = {(int64_t)N.ext[1] * N.ext[2], (int64_t)N.ext[1] * N.ext[2],
+                                    (int64_t)N.ext[0] * N.ext[2], (int64_t)N.ext[0] * N.ext[2],
+                                    (int64_t)N.ext[0] * N.ext[1], (int64_t)N.ext[0] * N.ext[1]};
+            int64_t no = 0;
+            for (int g = 0; g < (f ^ 1); ++g) no += nsz[g];
+            st = hip_status(hipMemcpyAsync(H + N.sr_off + N.face_total + no, base + B.sr_off + fo,
+                                           (size_t)fsz[f] * sizeof(double), hipMemcpyDeviceToHost, main),
+                            "face to host");
+            if (st != J3D_OK) return st;
+        }
+    }
+    // ... and each block's received faces back to the device
+    for (int32_t b = 0; b < nb; ++b) {
+        const BlockDesc &B = plan.blocks[b];
+        st = hip_status(hipMemcpyAsync(base + B.sr_off + B.face_total, H + B.sr_off + B.face_total,
+                                       (size_t)B.face_total * sizeof(double), hipMemcpyHostToDevice, main),
+                        "faces to device");
+        if (st != J3D_OK) return st;
+    }
+    if (overlap) {
+        st = join_side(s, main);
+        if (st != J3D_OK) return st;
+    }
+    st = hip_status(launch_unpack(base, blocks, 0, nb, plan.max_face, p, 0x3f, main), "unpack launch");
+    if (st != J3D_OK) return st;
+    if (overlap) return hip_status(launch_shell(base, blocks, 0, nb, s->max_shell, p, main), "shell launch");
+    return sweep_tiles(s, p, false, res, 0, s->ntiles, main);
+}
+
 // One sweep of `mode` reading parity p, enqueued on st.
 j3d_status one_sweep(j3d_solver *s, int mode, int p, bool res, int slot, hipStream_t st)
 {
@@ -483,6 +570,11 @@ j3d_status one_sweep(j3d_solver *s, int mode, int p, bool res, int slot, hipStre
         return run_per_block(s, p, res, 2, st);
     case J3D_BLOCK_C:
         return run_per_block(s, p, res, 3, st);
+    case J3D_HOST_STAGED:
+        return run_host_staged(s, p, res, false, st);
+    case J3D_HOST_OVERLAP:
+        // the overlapped update's shell pass carries no residual
+        return run_host_staged(s, p, res, !res, st);
     }
     return set_error(J3D_EINVAL, "unknown mode %d", mode);
 }
@@ -606,7 +698,8 @@ j3d_status j3d_run(j3d_solver *s, int64_t iters, j3d_mode mode_in, double *resid
         mode = J3D_FUSED;
         captured = true;
     }
-    if (mode < J3D_UNFUSED_BLOCK || mode > J3D_BLOCK_C) return set_error(J3D_EINVAL, "unknown mode %d", (int)mode_in);
+    if (mode < J3D_UNFUSED_BLOCK || mode > J3D_HOST_OVERLAP)
+        return set_error(J3D_EINVAL, "unknown mode %d", (int)mode_in);
     if (iters == 0) {
         if (residual_out) *residual_out = 0.0;
         return J3D_OK;
@@ -620,6 +713,10 @@ j3d_status j3d_run(j3d_solver *s, int64_t iters, j3d_mode mode_in, double *resid
         st = refresh_halos(s->plan, s->arena, 0, (int32_t)s->plan.blocks.size(), s->parity, s->stream);
         if (st != J3D_OK) return st;
         s->ghosts_fresh = true;
+    }
+    if (mode == J3D_HOST_STAGED || mode == J3D_HOST_OVERLAP) {
+        st = ensure_host_mirror(s);
+        if (st != J3D_OK) return st;
     }
     if (want_res) {
         st = hip_status(launch_fill_u64(res, 1, 0ull, s->stream), "residual reset");
@@ -692,6 +789,7 @@ j3d_status j3d_destroy(j3d_solver *s)
         if (s->join_ev[k]) (void)hipEventDestroy(s->join_ev[k]);
     }
     if (s->fork_ev) (void)hipEventDestroy(s->fork_ev);
+    if (s->host_sr) (void)hipHostFree(s->host_sr);
     delete s;
     return st;
 }

@@ -15,7 +15,8 @@ pytestmark = pytest.mark.gpu
 
 NTH = min(16, os.cpu_count() or 1)
 MODES = ("graph", "fused", "unfused_phase", "unfused_block", "block_a", "block_b", "block_c",
-         "unfused_block+graph", "block_a+graph", "block_b+graph", "block_c+graph", "unfused_phase+graph")
+         "unfused_block+graph", "block_a+graph", "block_b+graph", "block_c+graph", "unfused_phase+graph",
+         "host_staged", "host_overlap", "host_overlap+graph")
 
 
 @pytest.fixture(scope="module")
@@ -175,7 +176,8 @@ def test_resume_and_mode_switch(env):
         s.run(5, mode="graph")
         s.run(3, mode="block_c+graph")
         s.run(3, mode="block_a")
-        s.run(5, mode="unfused_phase")
+        s.run(2, mode="host_overlap")
+        s.run(3, mode="unfused_phase")
         r = s.run(7, mode="fused", residual=True)
         assert s.iters_done() == 30
         assert np.array_equal(s.get_interior(), want) and r == want_r
@@ -223,7 +225,7 @@ def test_errors_leave_state_untouched(env):
             j3d.j3d_set_tune(s.h, 999, 0, 0)
         with pytest.raises(j3d.J3DError):
             j3d.j3d_set_face(s.h, 6, 0, False)
-        for bad_mode in (7, 8, 15, 3 | 16 | 32, -1):
+        for bad_mode in (9, 15, 3 | 16 | 32, -1):
             with pytest.raises(j3d.J3DError) as e:
                 s.run(2, mode=bad_mode)
             assert e.value.status == j3d.J3D_EINVAL
