@@ -99,6 +99,21 @@ def test_one_cell_thick_blocks_and_tiny_grids(env):
     check(oracle, api, (130, 1, 2), nblk=(2, 1, 2), split=([1, 129], None, None), iters=6, mode="fused")
 
 
+def test_overlap_shell_recompute_on_thin_blocks(env):
+    # the overlapped host-staged mode recomputes each block's one-cell shell;
+    # blocks 1, 2 and 3 cells thick along each axis take every branch of its
+    # cell enumeration
+    oracle, api, _ = env
+    cases = [((5, 4, 3), (5, 4, 3), None),
+             ((9, 7, 8), (3, 3, 3), ([1, 2, 6], [3, 2, 2], [2, 1, 5])),
+             ((12, 3, 10), (2, 1, 2), ([2, 10], None, [1, 9])),
+             ((6, 11, 2), (3, 2, 1), ([2, 3, 1], [4, 7], None))]
+    for n, nblk, split in cases:
+        bc = (0.5, -1.0, 0.25, 2.0, -0.125, 1.0)
+        for mode in ("host_overlap", "host_overlap+graph"):
+            check(oracle, api, n, nblk=nblk, split=split, bc=bc, iters=9, mode=mode, seed=4)
+
+
 def test_every_tile_shape_and_schedule(env):
     oracle, api, j3d = env
     n = (150, 70, 37)
