@@ -284,7 +284,8 @@ j3d_status j3d_pool_step(j3d_pool *pl, int32_t sweeps);
 j3d_status j3d_pool_set_policy(j3d_pool *pl, int64_t fill_cells, int32_t max_wait_rounds);
 
 /* Sweep kernel shape of the pool's rounds: variant (-1 keeps the default
- * 64 x 32 tile) and zchunk (>= 1 planes per tile); blocks_per_cu must be 0.
+ * flattened 512-thread tile) and zchunk (>= 1 planes per tile, default 32);
+ * blocks_per_cu must be 0.
  * NULL restores the default.  ESTATE unless every slot is free (a request's
  * tile count is checked against the pool's tile table at admission).       */
 j3d_status j3d_pool_set_tune(j3d_pool *pl, const j3d_tune *t);

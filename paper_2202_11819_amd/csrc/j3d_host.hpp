@@ -76,6 +76,10 @@ void default_tune(const Plan &plan, int cus, j3d_tune *t);
 
 // Number of tiles that variant/zchunk give over the blocks of a plan.
 uint64_t count_tiles(const Plan &plan, int variant, int zchunk);
+// Index of the fixed-tile variant of this shape, or of the flattened variant
+// with this thread count, cell capacity and prefetch depth; -1 if none.
+int find_variant(int tile_x, int tile_y, int threads);
+int find_flat_variant(int threads, int cells, int prefetch);
 // Tiles of a block's x-y plane under variant vi: ntx along x, nty along y.
 inline void tiles_xy(const VariantInfo &vi, int64_t ex, int64_t ey, int64_t *ntx, int64_t *nty)
 {

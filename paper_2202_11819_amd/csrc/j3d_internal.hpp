@@ -102,24 +102,27 @@ int variant_count();
 VariantInfo variant_info(int v);
 
 // ---- flattened tiles ------------------------------------------------------------
-// A flattened tile covers nxv x nyv cells of an x-y plane, numbered x fastest
-// and dealt to the threads in that order, so every lane has a cell whatever
+// A flattened tile covers nxv x nyv cells of an x-y plane.  Its rows are dealt
+// to the threads in order, each row padded to a multiple of 16 lanes (one
+// 128-byte line of doubles), so a row starts on a line boundary in memory and
+// on a 16-lane boundary in the wave, and at most 15 lanes per row idle whatever
 // the block's width.  Per block, x is cut into tnx pieces of at most
 // flat_max_x(nt) columns (each after the first starting on a 16-column
-// boundary, so rows stay cache-line aligned) and y into tny near-equal pieces
-// of at most hy rows, with wx * hy <= cap (cells per thread budget) and
-// 2 * (wx + hy) <= nt (one thread per cell of the tile's halo ring), wx being
-// the widest x piece.  Host and kernels evaluate the same functions.
+// boundary) and y into tny near-equal pieces of at most hy rows, with
+// pad16(wx) * hy <= cap (cells per thread budget) and 2 * (wx + hy) <= nt (one
+// thread per cell of the tile's halo ring), wx being the widest x piece.  Host
+// and kernels evaluate the same functions.
 struct FlatShape {
     int tnx, tny, wx, hy;
 };
+constexpr int pad16(int x) { return (x + 15) / 16 * 16; }
 constexpr int flat_max_x(int nt) { return nt >= 512 ? 192 : nt / 2 - 32; }
 constexpr FlatShape flat_shape(int ex, int ey, int nt, int cap)
 {
     const int mx = flat_max_x(nt);
     const int tnx = (ex + mx - 1) / mx;
     const int wx = tnx == 1 ? ex : (ex + tnx - 1) / tnx + 15;
-    int hy = cap / wx;
+    int hy = cap / pad16(wx);
     if (nt / 2 - wx < hy) hy = nt / 2 - wx;
     if (ey < hy) hy = ey;
     if (hy < 1) hy = 1;

@@ -164,11 +164,13 @@ struct Tiled {
     static_assert(NT % 64 == 0, "whole waves");
     static_assert(PF >= 1 && PF <= 4, "prefetch depth");
     __device__ static int lx(int) { return LXC; }
+    __device__ static bool full(int nxv, int nyv) { return nxv == TX && nyv == TY; }
     template <bool FULL>
-    __device__ static bool cell(int tid, int r, int nxv, int nyv, int &cx, int &cy)
+    __device__ static bool cell(int tid, int r, int nxv, int nyv, bool, int &cx, int &cy, bool &pad)
     {
         cx = tid % TX;
         cy = tid / TX + NTY * r;
+        pad = false;
         return FULL || (cx < nxv && cy < nyv);
     }
     // ring cell of this thread: kind 0/1 = y-/y+ row (c = column), 2/3 = x-/x+ column (c = row)
@@ -194,9 +196,11 @@ struct Tiled {
     }
 };
 
-// Flattened tiles: the nxv*nyv cells of the rectangle are numbered x fastest
-// and cell f goes to thread f % NT, row f / NT; the rectangle is sized per
-// block by flat_shape, so no lane idles but those of the last partial wave.
+// Flattened tiles: the rectangle's rows, each padded to w = pad16(nxv) lanes,
+// are numbered x fastest and slot f goes to thread f % NT, row f / NT; the
+// rectangle is sized per block by flat_shape, so only the padding lanes of a
+// row and those of the last partial wave idle, and every row segment starts on
+// a cache line.
 template <int NT_, int RY_, int PF_>
 struct Flat {
     static constexpr int NT = NT_, RY = RY_, PF = PF_;
@@ -209,14 +213,20 @@ struct Flat {
     static_assert(NT % 64 == 0 && NT >= 256, "whole waves, room for a halo ring");
     static_assert(PF >= 1 && PF <= 4, "prefetch depth");
     __device__ static int lx(int nxv) { return nxv + 2; }
+    // every slot of every thread holds a cell (no padding lane, no idle tail)
+    __device__ static bool full(int nxv, int nyv) { return nxv % 16 == 0 && nxv * nyv == CAP; }
+    // pad: the slot is a padding lane of a row whose padding exists in memory
+    // (padok: the tile ends where the field's row padding starts)
     template <bool FULL>
-    __device__ static bool cell(int tid, int r, int nxv, int nyv, int &cx, int &cy)
+    __device__ static bool cell(int tid, int r, int nxv, int nyv, bool padok, int &cx, int &cy, bool &pad)
     {
+        const int w = pad16(nxv);
         const int f = tid + r * NT;
-        const bool v = f < nxv * nyv;
-        const int q = v ? f / nxv : 0;
-        cy = q;
-        cx = v ? f - q * nxv : 0;
+        const int q = f / w, x = f - q * w;
+        const bool v = q < nyv && x < nxv;
+        pad = padok && q < nyv && x >= nxv;
+        cy = v || pad ? q : 0;
+        cx = v || pad ? x : 0;
         return v;
     }
     __device__ static bool ring(int tid, int nxv, int nyv, int &kind, int &c)
@@ -280,17 +290,23 @@ __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *_
     // their LDS reads to a valid cell.
     constexpr uint32_t kOutside = 0x80000000u;
     bool vr[RY];
+    bool pd[RY];       // slot on the row padding after the tile's last column: it
+                       // stores back the value it loaded, so rows are written as
+                       // whole cache lines (no partial-line writes at row ends)
     uint32_t off[RY];  // byte offset of this thread's cell of row r inside a plane
     int lw[RY];        // LDS slot this thread writes for row r
     int li[RY];        // LDS slot of the cell (its four in-plane neighbours are +-1, +-lx)
     int ly[RY];        // row of the cell inside the tile
     bool fxm[RY], fxp[RY];  // cell on the block's x- / x+ face with a neighbour there (fused)
+    const bool padok = g.x0 + pad16(g.nxv) <= g.pitch;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         int cx, cy;
-        vr[r] = K::template cell<FULL>(tid, r, g.nxv, g.nyv, cx, cy);
-        off[r] = vr[r] ? (uint32_t)(g.y0 + cy + 1) * rowb + (uint32_t)(g.x0 + cx) * 8u : kOutside;
-        li[r] = (cy + 1) * lx + cx + 1;
+        bool pad;
+        vr[r] = K::template cell<FULL>(tid, r, g.nxv, g.nyv, padok, cx, cy, pad);
+        pd[r] = pad;
+        off[r] = vr[r] || pad ? (uint32_t)(g.y0 + cy + 1) * rowb + (uint32_t)(g.x0 + cx) * 8u : kOutside;
+        li[r] = vr[r] ? (cy + 1) * lx + cx + 1 : lx + 1;
         lw[r] = vr[r] ? li[r] : K::SINK + (tid & 63);
         ly[r] = cy;
         fxm[r] = vr[r] && g.xrm != 0 && g.x0 + cx == 0;
@@ -357,7 +373,7 @@ __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *_
             s += R[jm][r];
             s += R[jp][r];
             const double v = s * kW;
-            bstore<kAuxStore>(ro, off[r], v);
+            bstore<kAuxStore>(ro, off[r], pd[r] ? R[jc][r] : v);
             if (fxm[r]) XF[ly[r]] = v;
             if (fxp[r]) XF[K::XROWS + ly[r]] = v;
             if (g.want_res) {
@@ -518,8 +534,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
         }
     }
 
-    const int cells = g.nxv * g.nyv;
-    const bool full = cells == K::NT * K::RY;
+    const bool full = K::full(g.nxv, g.nyv);
     const double rmax = full ? sweep_planes<K, true>(g, hsrc0, hstep, hl, sm, xf)
                              : sweep_planes<K, false>(g, hsrc0, hstep, hl, sm, xf);
 

@@ -163,6 +163,17 @@ struct Bump {
     }
 };
 
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int max_ez(const Plan &plan, int32_t b0, int32_t b1)
+{
+    int m = 1;
+    for (int32_t b = b0; b < b1; ++b) m = plan.blocks[b].ext[2] > m ? plan.blocks[b].ext[2] : m;
+    return m;
+}
+
+}  // namespace
+
 int find_variant(int tile_x, int tile_y, int threads)
 {
     for (int v = 0; v < variant_count(); ++v) {
@@ -180,17 +191,6 @@ int find_flat_variant(int threads, int cells, int prefetch)
     }
     return -1;
 }
-
-int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
-
-int max_ez(const Plan &plan, int32_t b0, int32_t b1)
-{
-    int m = 1;
-    for (int32_t b = b0; b < b1; ++b) m = plan.blocks[b].ext[2] > m ? plan.blocks[b].ext[2] : m;
-    return m;
-}
-
-}  // namespace
 
 uint64_t count_tiles(const Plan &plan, int variant, int zchunk)
 {
@@ -320,27 +320,30 @@ void make_tiles(const Plan &plan, int32_t b0, int32_t b1, int variant, int zchun
 
 void default_tune(const Plan &plan, int cus, j3d_tune *t)
 {
-    // Shapes measured fastest on MI355X for each block width (one workgroup
-    // per tile; the persistent schedule never won for a single problem):
-    //   <= 64 wide: flattened tiles of 512 threads, 2 cells each (64 x 16 on
-    //               64-wide blocks), through 64 planes;
-    //   <= 128:     128 x 16 tiles of 512 threads, z-chunks of 32;
-    //   <= 160/192: a tile as wide as the widest block;
-    //   wider:      128 x 32 tiles of 1024 threads, z-chunks of 64.
+    // Shapes measured fastest on MI355X (one workgroup per tile; the
+    // persistent schedule never won for a single problem):
+    //   <= 64 wide:         flattened tiles of 512 threads, 2 cells each (64 x 16
+    //                       on 64-wide blocks), through 64 planes;
+    //   widths not a multiple of 16 (rows ending inside a cache line), or
+    //   129..192 wide:      flattened tiles of 512 threads, 4 cells each, which
+    //                       write whole lines at row ends, z-chunks of 32;
+    //   <= 128:             128 x 16 tiles of 512 threads, z-chunks of 32;
+    //   wider:              128 x 32 tiles of 1024 threads, z-chunks of 64.
     int exm = 1;
-    for (const BlockDesc &B : plan.blocks) exm = std::max(exm, B.ext[0]);
+    bool ragged = false;
+    for (const BlockDesc &B : plan.blocks) {
+        exm = std::max(exm, B.ext[0]);
+        ragged = ragged || B.ext[0] % 16 != 0;
+    }
     int v, zc;
     if (exm <= 64) {
         v = find_flat_variant(512, 1024, 3);
         zc = 64;
+    } else if (ragged || (exm > 128 && exm <= 192)) {
+        v = find_flat_variant(512, 2048, 1);
+        zc = 32;
     } else if (exm <= 128) {
         v = find_variant(128, 16, 512);
-        zc = 32;
-    } else if (exm <= 160) {
-        v = find_variant(160, 16, 640);
-        zc = 32;
-    } else if (exm <= 192) {
-        v = find_variant(192, 16, 768);
         zc = 32;
     } else {
         v = find_variant(128, 32, 1024);

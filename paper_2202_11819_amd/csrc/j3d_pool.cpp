@@ -24,7 +24,6 @@ namespace {
 
 // 64x32 tiles of 256 threads and 32-plane z-chunks: enough workgroups per
 // request that a round of a few mid-sized requests fills the GPU
-constexpr int kPoolVariantTileX = 64, kPoolVariantTileY = 32, kPoolVariantThreads = 512;
 constexpr int kPoolZchunk = 32;
 constexpr int64_t kPoolTilesPerReq = 4096;
 
@@ -72,15 +71,12 @@ Layout pool_layout(int32_t max_slots)
     return l;
 }
 
+// Requests come in every width, so rounds use flattened tiles (512 threads,
+// 4 cells each: rows of any width, whole cache lines written at row ends).
 int pool_variant()
 {
-    for (int v = 0; v < variant_count(); ++v) {
-        const VariantInfo vi = variant_info(v);
-        if (vi.tile_x == kPoolVariantTileX && vi.tile_y == kPoolVariantTileY &&
-            vi.threads == kPoolVariantThreads)
-            return v;
-    }
-    return 0;
+    const int v = find_flat_variant(512, 2048, 1);
+    return v >= 0 ? v : 0;
 }
 
 // Single-block request geometry and bytes.

@@ -348,7 +348,8 @@ def test_tune_roundtrip_and_default_shapes(env):
         s.set_tune(-1, 32, 0)  # -1: the default shape with the given chunking
         assert s.get_tune()[1:] == (32, 0) and s.get_tune()[0] == v
     # the default shape for other block widths
-    for n, nblk, tile in [((256, 256, 256), (2, 2, 2), (128, 16, 512)), ((320, 64, 64), (2, 1, 1), (160, 16, 640)),
-                          ((384, 64, 64), (2, 1, 1), (192, 16, 768)), ((256, 64, 64), (1, 1, 1), (128, 32, 1024))]:
+    for n, nblk, tile in [((256, 256, 256), (2, 2, 2), (128, 16, 512)), ((320, 64, 64), (2, 1, 1), (0, 2048, 512)),
+                          ((384, 64, 64), (2, 1, 1), (0, 2048, 512)), ((256, 64, 64), (1, 1, 1), (128, 32, 1024)),
+                          ((300, 64, 64), (1, 1, 1), (0, 2048, 512)), ((254, 64, 64), (2, 1, 1), (0, 2048, 512))]:
         with api.Solver(n, nblk=nblk, seed=1) as s:
             assert tuple(vs[s.get_tune()[0]]) == tile, (n, nblk)
