@@ -1,12 +1,16 @@
 // j3d_solver.cpp -- the plain solver and the batched form behind the C ABI.
 //
-// Iteration order (Fig. 1 without manual overlap, Fig. 3): pack the six halo
-// faces, exchange them, unpack, update the whole block.  The first iteration
-// of the fused path needs halos of the initial iterate, so a pack / exchange
-// / unpack runs once before it (Fig. 3 packs at the top of every iteration;
-// the fused kernel instead packs at the end of the previous one).  Host and
-// device never synchronise inside the iteration loop (Sec. III-C removes such
-// synchronisations); only a requested residual or a host copy waits.
+// Iteration order (Fig. 1, Fig. 3): pack the six halo faces, exchange them,
+// unpack, update the whole block.  The modes differ in how these steps become
+// GPU work: per block and face (no fusion, strategies A and B of
+// Sec. III-D-1), per phase for all blocks, through host memory (with or
+// without the update overlapping the transfers), or as one fused kernel per
+// block or for all blocks, which reads y and z halos across the block
+// boundary and hands its x faces over at the end of the previous sweep (so the
+// first fused sweep is preceded by one pack / exchange / unpack).  Any mode can
+// be captured into HIP graphs.  Host and device never synchronise inside the
+// iteration loop (Sec. III-C removes such synchronisations); only a requested
+// residual or a host copy waits.
 #include <algorithm>
 #include <climits>
 #include <cstdint>
