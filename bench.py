@@ -361,6 +361,8 @@ def main():
     ap.add_argument("--load", type=float, default=0.8, help="serve workload: arrival rate / serial capacity")
     ap.add_argument("--fill-cells", type=int, default=-1, help="serve workload: pool round policy (-1: default)")
     ap.add_argument("--pool-tune", default="", help="serve workload: variant,zchunk of the pool's rounds")
+    ap.add_argument("--backlog-share", type=int, default=-1,
+                    help="serve workload: rounds hold at least 1/k of the running cells (-1: default)")
     ap.add_argument("--odf-edge", type=int, default=256, help="odf workload: grid edge")
     ap.add_argument("--odf-sweeps", type=int, default=20, help="odf workload: timed sweeps per mode")
     args = ap.parse_args()

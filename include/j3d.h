@@ -277,11 +277,14 @@ j3d_status j3d_pool_step(j3d_pool *pl, int32_t sweeps);
 
 /* Round policy.  fill_cells > 0: requests join a round in order of least
  * remaining work (cells x sweeps left) until the round holds at least
- * fill_cells cells; a request left out of max_wait_rounds consecutive rounds
- * joins first.  fill_cells == 0: every running request joins every round.
- * Default: fill_cells = 2^25, max_wait_rounds = 32.  Results do not depend on
- * the policy, only latencies do.                                            */
-j3d_status j3d_pool_set_policy(j3d_pool *pl, int64_t fill_cells, int32_t max_wait_rounds);
+ * max(fill_cells, running cells / backlog_share) cells (backlog_share 0: just
+ * fill_cells), so rounds grow with the backlog; a request left out of
+ * max_wait_rounds consecutive rounds joins first.  fill_cells == 0: every
+ * running request joins every round.  Default: fill_cells = 2^25,
+ * max_wait_rounds = 32, backlog_share = 2.  Results do not depend on the
+ * policy, only latencies and throughput do.                                 */
+j3d_status j3d_pool_set_policy(j3d_pool *pl, int64_t fill_cells, int32_t max_wait_rounds,
+                               int32_t backlog_share);
 
 /* Sweep kernel shape of the pool's rounds: variant (-1 keeps the default
  * flattened 512-thread tile) and zchunk (>= 1 planes per tile, default 32);

@@ -140,8 +140,8 @@ class Pool:
     def step(self, sweeps=50):
         C.j3d_pool_step(self.h, sweeps)
 
-    def set_policy(self, fill_cells, max_wait_rounds=32):
-        C.j3d_pool_set_policy(self.h, fill_cells, max_wait_rounds)
+    def set_policy(self, fill_cells, max_wait_rounds=32, backlog_share=0):
+        C.j3d_pool_set_policy(self.h, fill_cells, max_wait_rounds, backlog_share)
 
     def set_tune(self, variant=-1, zchunk=32):
         """Tile shape of the rounds; only while no request is admitted."""

@@ -118,6 +118,7 @@ struct j3d_pool {
     // a request left out of max_wait consecutive rounds joins first
     int64_t fill_cells = int64_t(1) << 25;
     int32_t max_wait = 32;
+    int32_t backlog_share = 2;  // > 0: the target is at least 1/backlog_share of the running cells
 };
 
 namespace {
@@ -379,9 +380,19 @@ j3d_status j3d_pool_step(j3d_pool *pl, int32_t sweeps)
         return a.slot < b.slot;
     });
     std::vector<char> chosen(pl->max_slots, 0);
+    int64_t target = pl->fill_cells;
+    if (target > 0 && pl->backlog_share > 0) {
+        // under a backlog, larger rounds: fewer, longer launches serve more cells per second
+        int64_t running = 0;
+        for (const Cand &c : cands) {
+            const Req &r = pl->reqs[c.slot];
+            running += r.n[0] * r.n[1] * r.n[2];
+        }
+        target = std::max(target, running / pl->backlog_share);
+    }
     int64_t cells = 0;
     for (const Cand &c : cands) {
-        if (pl->fill_cells > 0 && cells >= pl->fill_cells) break;
+        if (target > 0 && cells >= target) break;
         chosen[c.slot] = 1;
         const Req &r = pl->reqs[c.slot];
         cells += r.n[0] * r.n[1] * r.n[2];
@@ -501,14 +512,15 @@ j3d_status j3d_pool_result(j3d_pool *pl, int32_t slot, double *residual, int64_t
     return J3D_OK;
 }
 
-j3d_status j3d_pool_set_policy(j3d_pool *pl, int64_t fill_cells, int32_t max_wait_rounds)
+j3d_status j3d_pool_set_policy(j3d_pool *pl, int64_t fill_cells, int32_t max_wait_rounds, int32_t backlog_share)
 {
     if (!pl) return set_error(J3D_EINVAL, "pool is NULL");
-    if (fill_cells < 0 || max_wait_rounds < 1)
-        return set_error(J3D_EINVAL, "fill_cells %lld < 0 or max_wait_rounds %d < 1", (long long)fill_cells,
-                         max_wait_rounds);
+    if (fill_cells < 0 || max_wait_rounds < 1 || backlog_share < 0)
+        return set_error(J3D_EINVAL, "fill_cells %lld < 0, max_wait_rounds %d < 1 or backlog_share %d < 0",
+                         (long long)fill_cells, max_wait_rounds, backlog_share);
     pl->fill_cells = fill_cells;
     pl->max_wait = max_wait_rounds;
+    pl->backlog_share = backlog_share;
     return J3D_OK;
 }
 

@@ -38,13 +38,13 @@ def nearest_rank(values, q):
 
 
 def serve_pool(trace, budget_bytes, max_slots=256, round_sweeps=50, check_every=50, tol=0.0,
-               keep_results=False, log=None, fill_cells=None, tune=None):
+               keep_results=False, log=None, fill_cells=None, tune=None, backlog_share=None):
     """Serve `trace` (list of workloads.Request) in real time; per-request records.
-    fill_cells: round policy, tune: (variant, zchunk) of the rounds (None keeps
-    the library defaults)."""
+    fill_cells, backlog_share: round policy, tune: (variant, zchunk) of the
+    rounds (None keeps the library defaults)."""
     pool = Pool(budget_bytes, max_slots=max_slots)
-    if fill_cells is not None:
-        pool.set_policy(fill_cells)
+    if fill_cells is not None or backlog_share is not None:
+        pool.set_policy(1 << 25 if fill_cells is None else fill_cells, 32, 2 if backlog_share is None else backlog_share)
     if tune is not None:
         pool.set_tune(*tune)
     problems = [W.to_problem(r.spec) for r in trace]
@@ -153,9 +153,11 @@ def bench_serve(args):
     free = torch.cuda.mem_get_info()[0]
     budget = int(min(200e9, 0.85 * free))
     fill = int(getattr(args, "fill_cells", -1))
+    share = int(getattr(args, "backlog_share", -1))
     ptune = getattr(args, "pool_tune", "")
     ptune = tuple(int(v) for v in ptune.split(",")) if ptune else None
-    recs, rounds = serve_pool(trace, budget, log=_log, fill_cells=None if fill < 0 else fill, tune=ptune)
+    recs, rounds = serve_pool(trace, budget, log=_log, fill_cells=None if fill < 0 else fill, tune=ptune,
+                              backlog_share=None if share < 0 else share)
     pool_sum = summarize(recs, warmup)
     srecs = serve_serial(trace, log=_log)
     serial_sum = summarize(srecs, warmup)
@@ -167,6 +169,7 @@ def bench_serve(args):
     out = {"metric": "served solves/s and p50/p99 latency (arrival to result on host)",
            "value": pool_sum["solves_per_s"], "unit": "solves/s", "higher_is_better": True,
            "pool": pool_sum, "serial_plain": serial_sum, "rounds": rounds, "fill_cells": fill,
+           "backlog_share": share,
            "pool_tune": list(ptune) if ptune else None,
            "config": {"workload": f"{count} Jacobi3D solve requests, Poisson arrivals at {rate:.2f}/s "
                                   f"({load} x serial capacity), per-axis size U{{32..384}}, 50..2000 sweeps, "

@@ -170,6 +170,11 @@ def test_pool_tune_only_while_empty(env):
                 pool.step(50)
         pool.release(slot)
         pool.set_tune(3, 32)
+        for bad in [(-1, 32, 0), (1 << 20, 0, 0), (1 << 20, 4, -1)]:
+            with pytest.raises(j3d.J3DError) as e:
+                pool.set_policy(*bad)
+            assert e.value.status == j3d.J3D_EINVAL
+        pool.set_policy(1 << 22, 8, 4)
         for bad in [(len(j3d.variants()), 32), (3, 0)]:
             with pytest.raises(j3d.J3DError) as e:
                 pool.set_tune(*bad)
