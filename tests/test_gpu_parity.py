@@ -298,6 +298,29 @@ def test_overdecomposed_512_full_run_matches_oracle(env):
     assert np.array_equal(got, want), f"max |diff| {np.abs(got - want).max()}"
 
 
+@pytest.mark.slow
+def test_block_sweep_1024_full_runs_match_oracle(env):
+    # The decomposition benchmark at its real size: 1024^3, 500 sweeps, as 4^3,
+    # 8^3 and 16^3 blocks and the uneven split, each in graph mode with the
+    # residual, against one oracle run of the undivided grid (about 50 s on
+    # 16 host threads and 26 GB of host memory).
+    oracle, api, _ = env
+    from paper_2202_11819_amd import workloads as W
+    cases = W.block_sweep()
+    n, t = cases[0][1].n, cases[0][1].iters
+    say(f"oracle: {n} x {t} sweeps")
+    want, want_r, _ = oracle.jacobi(n, t, seed=cases[0][1].seed, nthreads=NTH)
+    for label, spec in cases:
+        assert spec.n == n and spec.iters == t
+        say(label)
+        with api.Solver(spec.n, nblk=spec.nblk, split=spec.split, seed=spec.seed) as s:
+            r = s.run(t, mode="graph", residual=True)
+            got = s.get_interior()
+        assert r == want_r, label
+        assert np.array_equal(got, want), label
+        del got
+
+
 def test_overdecomposed_512_eigenmode_bound(env):
     # Lowest sine mode with zero boundary decays by lambda per sweep.
     import math
