@@ -359,6 +359,8 @@ def main():
     ap.add_argument("--serve-dump", default="", help="serve workload: write per-request records here")
     ap.add_argument("--retune", action="store_true", help="batch workload: ignore the tuning cache")
     ap.add_argument("--load", type=float, default=0.8, help="serve workload: arrival rate / serial capacity")
+    ap.add_argument("--tol", type=float, default=0.0,
+                    help="serve workload: stop a request at the first residual check with r <= tol (0: never)")
     ap.add_argument("--fill-cells", type=int, default=-1, help="serve workload: pool round policy (-1: default)")
     ap.add_argument("--pool-tune", default="", help="serve workload: variant,zchunk of the pool's rounds")
     ap.add_argument("--backlog-share", type=int, default=-1,

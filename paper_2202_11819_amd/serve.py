@@ -97,21 +97,34 @@ def serve_pool(trace, budget_bytes, max_slots=256, round_sweeps=50, check_every=
     return recs, rounds
 
 
-def serve_serial(trace, log=None, keep_results=False):
-    """The same trace, one plain solve at a time in arrival order."""
+def serve_serial(trace, log=None, keep_results=False, tol=0.0, check_every=50):
+    """The same trace, one plain solve at a time in arrival order.  With tol > 0
+    a solve runs in pieces of check_every sweeps (the last one shorter), reads
+    the residual after each and stops at the first r <= tol, the same rule the
+    pool applies."""
     recs = []
     finish = 0.0
     for i, r in enumerate(trace):
         t0 = time.perf_counter()
         s = Solver(r.spec.n, nblk=r.spec.nblk, bc=r.spec.bc, seed=r.spec.seed, pid=r.spec.pid)
-        res = s.run(r.spec.iters, mode="graph", residual=True)
+        if tol > 0:
+            done = 0
+            while True:
+                k = min(check_every, r.spec.iters - done)
+                res = s.run(k, mode="graph", residual=True)
+                done += k
+                if res <= tol or done >= r.spec.iters:
+                    break
+        else:
+            res = s.run(r.spec.iters, mode="graph", residual=True)
+            done = r.spec.iters
         u = s.get_interior()
         s.close()
         service = time.perf_counter() - t0
         start = max(r.arrival, finish)
         finish = start + service
         rec = {"i": i, "arrival": r.arrival, "done": finish, "latency": finish - r.arrival, "service": service,
-               "residual": res, "iters": r.spec.iters, "cells": int(np.prod(r.spec.n))}
+               "residual": res, "iters": done, "cells": int(np.prod(r.spec.n))}
         if keep_results:
             rec["u"] = u
         recs.append(rec)
@@ -156,11 +169,18 @@ def bench_serve(args):
     share = int(getattr(args, "backlog_share", -1))
     ptune = getattr(args, "pool_tune", "")
     ptune = tuple(int(v) for v in ptune.split(",")) if ptune else None
+    tol = float(getattr(args, "tol", 0.0) or 0.0)
     recs, rounds = serve_pool(trace, budget, log=_log, fill_cells=None if fill < 0 else fill, tune=ptune,
-                              backlog_share=None if share < 0 else share)
+                              backlog_share=None if share < 0 else share, tol=tol)
     pool_sum = summarize(recs, warmup)
-    srecs = serve_serial(trace, log=_log)
+    srecs = serve_serial(trace, log=_log, tol=tol)
     serial_sum = summarize(srecs, warmup)
+    # every request served in the mix against the same request solved alone:
+    # the last sweep's residual (bit pattern) and the sweep count must agree
+    same_res = sum(1 for a, b in zip(recs, srecs)
+                   if np.float64(a["residual"]).tobytes() == np.float64(b["residual"]).tobytes())
+    same_it = sum(1 for a, b in zip(recs, srecs) if a["iters"] == b["iters"])
+    early = sum(1 for a, r in zip(recs, trace) if a["iters"] < r.spec.iters)
     dump = getattr(args, "serve_dump", "")
     if dump:
         with open(dump, "w") as f:
@@ -169,11 +189,13 @@ def bench_serve(args):
     out = {"metric": "served solves/s and p50/p99 latency (arrival to result on host)",
            "value": pool_sum["solves_per_s"], "unit": "solves/s", "higher_is_better": True,
            "pool": pool_sum, "serial_plain": serial_sum, "rounds": rounds, "fill_cells": fill,
+           "mix_vs_alone": {"requests": len(recs), "residual_bit_identical": same_res,
+                            "sweeps_identical": same_it, "stopped_early": early},
            "backlog_share": share,
            "pool_tune": list(ptune) if ptune else None,
            "config": {"workload": f"{count} Jacobi3D solve requests, Poisson arrivals at {rate:.2f}/s "
                                   f"({load} x serial capacity), per-axis size U{{32..384}}, 50..2000 sweeps, "
-                                  f"residual every 50, tol 0, budget {budget / 1e9:.0f} GB, "
+                                  f"residual every 50, tol {tol:g}, budget {budget / 1e9:.0f} GB, "
                                   f"first {warmup} discarded", "dtype": "f64"}}
     print(json.dumps(out), flush=True)
 

@@ -154,6 +154,30 @@ def test_pool_early_exit_matches_checked_oracle(env):
         pool.release(slot)
 
 
+def test_serial_checked_solves_match_pool_and_oracle(env):
+    # The served benchmark's serial baseline with a tolerance: pieces of 50
+    # sweeps with a residual read after each, stopping at the first r <= tol.
+    # It must stop where the pool and the oracle's checked run stop.
+    oracle, api, j3d, W = env
+    from paper_2202_11819_amd import serve
+    specs = [W.Spec(n=(30, 26, 22), seed=6, pid=0, iters=500), W.Spec(n=(17, 40, 9), seed=6, pid=1, iters=130),
+             W.Spec(n=(24, 24, 24), seed=6, pid=2, iters=75)]
+    _, tol, _ = oracle.jacobi(specs[0].n, 120, seed=6, pid=0)
+    trace = [W.Request(arrival=0.0, spec=s) for s in specs]
+    srecs = serve.serve_serial(trace, keep_results=True, tol=tol, check_every=50)
+    precs, _ = serve.serve_pool(trace, budget_bytes=1 << 30, max_slots=4, keep_results=True, tol=tol,
+                                check_every=50)
+    stopped = 0
+    for s, a, b in zip(specs, srecs, precs):
+        want, want_r, done = oracle.jacobi(s.n, s.iters, seed=s.seed, pid=s.pid, tol=tol, check_every=50,
+                                           nthreads=NTH)
+        stopped += done < s.iters
+        assert a["iters"] == b["iters"] == done, s
+        assert a["residual"] == b["residual"] == want_r, s
+        assert np.array_equal(a["u"], want) and np.array_equal(b["u"], want), s
+    assert stopped >= 1
+
+
 def test_pool_tune_only_while_empty(env):
     _, api, j3d, _ = env
     with api.Pool(1 << 30, max_slots=2) as pool:
