@@ -160,8 +160,8 @@ const char *j3d_version(void);
  * which sets the communication volume, is smallest).  Only factorisations
  * with nblk[a] <= n[a] are considered; ties go to the one with the most
  * blocks along z, then along y.  The chosen counts need not divide n[a]:
- * uneven extents follow the j3d_block_extents rule.  EINVAL if parts < 1 or
- * no factorisation fits.                                                     */
+ * uneven extents follow the j3d_block_extents rule.  EINVAL if parts < 1,
+ * parts > 2^22 (the block limit of a problem) or no factorisation fits.      */
 j3d_status j3d_auto_split(const int64_t n[3], int32_t parts, int32_t nblk_out[3]);
 
 /* Resolved decomposition of a problem: nblk_out[3] blocks per axis and, if

@@ -43,10 +43,11 @@ uint64_t stream_start(uint64_t seed, uint64_t pid)
 j3d_status auto_split(const int64_t n[3], int32_t parts, int32_t nb[3])
 {
     if (parts < 1) return set_error(J3D_EINVAL, "auto split: parts must be >= 1 (got %d)", parts);
+    if (parts > (1 << 22)) return set_error(J3D_EINVAL, "auto split: %d blocks, more than 2^22", parts);
     bool found = false;
     unsigned __int128 best = 0;
     int32_t bc[3] = {0, 0, 0};
-    for (int32_t a = 1; a <= parts; ++a) {
+    for (int32_t a = 1; a <= parts && a <= n[0]; ++a) {
         if (parts % a) continue;
         for (int32_t b = 1; b <= parts / a; ++b) {
             if ((parts / a) % b) continue;

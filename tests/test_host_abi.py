@@ -69,6 +69,12 @@ def test_auto_split_prefers_small_surface():
     with pytest.raises(j3d.J3DError) as e:
         j3d.j3d_auto_split((2, 2, 2), 27)
     assert e.value.status == j3d.J3D_EINVAL
+    # more parts than a problem may have blocks: rejected at once, not searched
+    for parts in ((1 << 22) + 1, 2**31 - 1):
+        with pytest.raises(j3d.J3DError) as e:
+            j3d.j3d_auto_split((1 << 30,) * 3, parts)
+        assert e.value.status == j3d.J3D_EINVAL
+    assert j3d.j3d_auto_split((1 << 30,) * 3, 1 << 21) == (1 << 7,) * 3
 
 
 def test_block_extents_rules():
