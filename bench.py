@@ -339,13 +339,48 @@ def bench_hostex(args):
         torch.cuda.empty_cache()
 
 
+def bench_twostep(args):
+    """Two sweeps per launch against one, on the same grid left undivided (--edge, --sweeps)."""
+    import torch
+    from paper_2202_11819_amd import api
+
+    n = (args.edge,) * 3
+    cells = args.edge ** 3
+    sweeps = args.sweeps - args.sweeps % 2
+    with api.Solver(n, seed=1) as s:
+        u0 = s.get_interior_device()
+        for mode in ("graph", "two_sweep"):
+            s.set_interior(u0)
+            s.run(10, mode=mode)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            s.run(sweeps, mode=mode)
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            per_launch = 2 if mode == "two_sweep" else 1
+            launches = sweeps // per_launch
+            # algorithmic bytes per launch: each cell read and written once, plus the boundary layer read
+            nbytes = 16 * cells + 16 * 3 * args.edge ** 2
+            gbps = nbytes * launches / (ms * 1e-3) / 1e9
+            print(json.dumps({"metric": "FP64 Jacobi3D GLUP/s, one vs two sweeps per launch", "grid": list(n),
+                              "blocks": [1, 1, 1], "mode": mode, "sweeps": sweeps,
+                              "value": round(cells * sweeps / ms / 1e6, 2), "unit": "GLUP/s",
+                              "ms_per_sweep": round(ms / sweeps, 4), "sweeps_per_launch": per_launch,
+                              "launch_ms": round(ms / launches, 4), "bytes_per_launch": nbytes,
+                              "GBps": round(gbps, 1), "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4)}), flush=True)
+        del u0
+    torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="overdecomposed",
-                    choices=["overdecomposed", "modes", "sweep", "batch", "serve", "odf", "hostex"])
+                    choices=["overdecomposed", "modes", "sweep", "batch", "serve", "odf", "hostex", "twostep"])
     ap.add_argument("--mode", default="graph", choices=["graph", "fused", "unfused_phase", "unfused_block"])
     ap.add_argument("--edge", type=int, default=512)
     ap.add_argument("--blocks", type=int, default=8)
@@ -390,6 +425,8 @@ def main():
         bench_odf(args)
     elif args.workload == "hostex":
         bench_hostex(args)
+    elif args.workload == "twostep":
+        bench_twostep(args)
 
 
 if __name__ == "__main__":

@@ -91,6 +91,13 @@ typedef enum {
  *                 the faces are in transit (Fig. 1's overlap of computation
  *                 and communication); the cells that read a halo are then
  *                 recomputed from the delivered halos.
+ *  TWO_SWEEP:     two iterations per launch (temporal blocking) on a grid of
+ *                 one block: each workgroup computes the intermediate iterate
+ *                 on its tile plus a one-cell ring in LDS and writes only
+ *                 every second iterate, halving the HBM traffic per
+ *                 iteration.  An odd count ends with one FUSED sweep.  EINVAL
+ *                 for a decomposed grid or with CAPTURED.  Not in the paper;
+ *                 it applies where no block boundary needs an exchange.
  *  CAPTURED:      a flag OR-ed with any mode: its iterations are captured once
  *                 into HIP graphs (50 sweeps per graph for FUSED, 2 for the
  *                 others, whose graphs hold thousands of nodes) and replayed;
@@ -105,6 +112,7 @@ typedef enum {
     J3D_BLOCK_C = 6,
     J3D_HOST_STAGED = 7,
     J3D_HOST_OVERLAP = 8,
+    J3D_TWO_SWEEP = 9,
     J3D_CAPTURED = 16
 } j3d_mode;
 

@@ -133,6 +133,22 @@ constexpr int flat_x0(int ex, int tnx, int tx)
     return tx == 0 ? 0 : tx >= tnx ? ex : (int)(((int64_t)tx * ex / tnx) & ~(int64_t)15);
 }
 
+// Two sweeps per launch on a grid of one block (j3d_twostep.hip).  The
+// launch reads iterate t from `cur` and writes iterate t+2 to `nxt`; x-y tiles
+// of 64 x 16 cells, z cut into ntz near-equal pieces.
+struct TwoStepArgs {
+    const double *cur;        // field of iterate t (plane index 0: the z- ghost plane)
+    double *nxt;              // field that receives iterate t+2
+    const double *xh;         // x-halo arrays (x- then x+, ey*ez each, y fastest)
+    unsigned long long *res;  // residual word of the second sweep (bit pattern)
+    int32_t ex, ey, ez, pitch;
+    int32_t ntx, nty, ntz;
+    int32_t want_res;
+};
+// Tile counts for a block and z-chunk (0 or >= ez: whole planes); returns the total.
+int twostep_tiles(int ex, int ey, int ez, int zchunk, int *ntx, int *nty, int *ntz);
+int launch_twostep(const TwoStepArgs &a, void *stream);
+
 // ---- launchers (defined in j3d_kernels.hip); all enqueue on `stream` ----------
 // Every launcher returns 0 or a hipError_t value.
 

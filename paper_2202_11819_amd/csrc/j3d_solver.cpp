@@ -583,6 +583,67 @@ j3d_status one_sweep(j3d_solver *s, int mode, int p, bool res, int slot, hipStre
     return set_error(J3D_EINVAL, "unknown mode %d", mode);
 }
 
+// TWO_SWEEP: iters / 2 launches of the two-sweep kernel (each reads the
+// current buffer and writes the other), then one fused sweep if iters is
+// odd.  The residual comes from the launch that performs the last sweep.
+j3d_status run_two_sweep(j3d_solver *s, int64_t iters, bool want_res, unsigned long long *res)
+{
+    const BlockDesc &B = s->plan.blocks[0];
+    double *base = reinterpret_cast<double *>(s->arena);
+    TwoStepArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.ex = B.ext[0];
+    a.ey = B.ext[1];
+    a.ez = B.ext[2];
+    a.pitch = B.pitch;
+    a.res = res;
+    // whole planes when the x-y tiles alone give every compute unit a
+    // workgroup, else z-chunks for about two workgroups per compute unit
+    int ntx = 0, nty = 0, ntz = 0;
+    twostep_tiles(a.ex, a.ey, a.ez, 0, &ntx, &nty, &ntz);
+    int zc = 0;
+    if (ntx * nty < s->cus) {
+        const int want = (2 * s->cus + ntx * nty - 1) / (ntx * nty);
+        zc = std::max(4, (a.ez + want - 1) / want);
+    }
+    twostep_tiles(a.ex, a.ey, a.ez, zc, &a.ntx, &a.nty, &a.ntz);
+    int p = s->parity;
+    const int64_t pairs = iters / 2;
+    for (int64_t k = 0; k < pairs; ++k) {
+        a.cur = base + B.off[p];
+        a.nxt = base + B.off[p ^ 1];
+        a.xh = base + B.xoff[p];
+        a.want_res = want_res && (iters & 1) == 0 && k + 1 == pairs;
+        j3d_status st = hip_status(launch_twostep(a, s->stream), "two-sweep launch");
+        if (st != J3D_OK) return st;
+        p ^= 1;
+    }
+    if (iters & 1) {
+        const int slot = persistent_mode(s, J3D_FUSED) ? (int)(s->persist_launches++ & 1) : 0;
+        j3d_status st = one_sweep(s, J3D_FUSED, p, want_res, slot, s->stream);
+        if (st != J3D_OK) return st;
+        p ^= 1;
+    }
+    s->parity = p;
+    s->iters_done += iters;
+    return J3D_OK;
+}
+
+// Read back a requested residual (synchronises) after a run.
+j3d_status finish_run(j3d_solver *s, double *residual_out, const unsigned long long *res)
+{
+    if (!residual_out) return J3D_OK;
+    unsigned long long bits = 0;
+    j3d_status st = hip_status(hipMemcpyAsync(&bits, res, sizeof bits, hipMemcpyDeviceToHost, s->stream),
+                               "residual readback");
+    if (st == J3D_OK) st = hip_status(hipStreamSynchronize(s->stream), "residual readback");
+    if (st != J3D_OK) return st;
+    double r;
+    std::memcpy(&r, &bits, sizeof r);
+    *residual_out = r;
+    return J3D_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -702,8 +763,14 @@ j3d_status j3d_run(j3d_solver *s, int64_t iters, j3d_mode mode_in, double *resid
         mode = J3D_FUSED;
         captured = true;
     }
-    if (mode < J3D_UNFUSED_BLOCK || mode > J3D_HOST_OVERLAP)
+    if (mode < J3D_UNFUSED_BLOCK || mode > J3D_TWO_SWEEP)
         return set_error(J3D_EINVAL, "unknown mode %d", (int)mode_in);
+    if (mode == J3D_TWO_SWEEP) {
+        if (captured) return set_error(J3D_EINVAL, "the two-sweep mode is not captured into graphs");
+        if (s->plan.blocks.size() != 1)
+            return set_error(J3D_EINVAL, "the two-sweep mode needs a grid of one block (%zu blocks)",
+                             s->plan.blocks.size());
+    }
     if (iters == 0) {
         if (residual_out) *residual_out = 0.0;
         return J3D_OK;
@@ -711,6 +778,15 @@ j3d_status j3d_run(j3d_solver *s, int64_t iters, j3d_mode mode_in, double *resid
     const bool want_res = residual_out != nullptr;
     unsigned long long *res = reinterpret_cast<unsigned long long *>(s->arena + s->plan.off_res);
     j3d_status st = J3D_OK;
+    if (mode == J3D_TWO_SWEEP) {
+        if (want_res) {
+            st = hip_status(launch_fill_u64(res, 1, 0ull, s->stream), "residual reset");
+            if (st != J3D_OK) return st;
+        }
+        st = run_two_sweep(s, iters, want_res, res);
+        if (st != J3D_OK) return st;
+        return finish_run(s, residual_out, res);
+    }
     // modes that read x halos where the previous fused sweep handed them over
     const bool fused = mode == J3D_FUSED || mode == J3D_BLOCK_C;
     if (fused && !s->ghosts_fresh) {
@@ -754,17 +830,7 @@ j3d_status j3d_run(j3d_solver *s, int64_t iters, j3d_mode mode_in, double *resid
     s->parity = p;
     s->iters_done += iters;
     s->ghosts_fresh = fused;
-    if (want_res) {
-        unsigned long long bits = 0;
-        st = hip_status(hipMemcpyAsync(&bits, res, sizeof bits, hipMemcpyDeviceToHost, s->stream),
-                        "residual readback");
-        if (st == J3D_OK) st = hip_status(hipStreamSynchronize(s->stream), "residual readback");
-        if (st != J3D_OK) return st;
-        double r;
-        std::memcpy(&r, &bits, sizeof r);
-        *residual_out = r;
-    }
-    return J3D_OK;
+    return finish_run(s, residual_out, res);
 }
 
 j3d_status j3d_iters_done(const j3d_solver *s, int64_t *iters)

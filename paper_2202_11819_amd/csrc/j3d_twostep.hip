@@ -1,0 +1,258 @@
+// j3d_twostep.hip -- two Jacobi sweeps per launch on an undivided grid.
+//
+// Temporal blocking along the marching axis: a workgroup owns an x-y tile of
+// the grid and walks up z.  For each plane it first computes the intermediate
+// iterate v = u^{t+1} over the tile and a one-cell ring around it, from u^t
+// over the tile and a two-cell ring, and then the result w = u^{t+2} over the
+// tile, one plane behind.  u^t is read from HBM once and u^{t+2} written
+// once, so a cell update costs 8 bytes of HBM traffic instead of 16; the
+// intermediate iterate lives only in LDS.  Each value of v and w is the
+// 7-term sum of the same operands in the same order as a single sweep
+// (centre, x-, x+, y-, y+, z-, z+, each addition rounded, then one
+// multiplication by fl(1/7); built with -ffp-contract=off), so the result is
+// bit-identical to two separate sweeps.
+//
+// Only a grid of one block is handled here: every halo value is then a
+// Dirichlet value held in the block's own ghost rows, ghost planes and x-halo
+// arrays, which never change.  Ring cells of v that lie on the boundary
+// layer keep their Dirichlet value.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "j3d_internal.hpp"
+
+namespace j3d {
+namespace {
+
+constexpr double kW2 = 1.0 / 7.0;  // fl(1/7)
+constexpr int kXcds2 = 8;          // XCDs per MI355X
+
+constexpr int TX = 64, TY = 16, NT = 512;
+constexpr int UX = TX + 4, UY = TY + 4, UP = UX * UY;  // u^t: tile with a two-cell ring
+constexpr int VX = TX + 2, VY = TY + 2, VP = VX * VY;  // v: tile with a one-cell ring
+constexpr int US = (UP + NT - 1) / NT;                 // u cells per thread and plane
+constexpr int VS = (VP + NT - 1) / NT;                 // v cells per thread and plane
+constexpr int WS = TX * TY / NT;                       // w cells per thread and plane
+constexpr int USLOT = US * NT;                         // LDS doubles per u plane (every lane writes)
+constexpr int VSLOT = VS * NT;
+constexpr int NB = 3;                                  // planes of u held in registers per lane
+static_assert(TX * TY % NT == 0, "whole w rows per thread");
+static_assert(US == 3 && VS == 3 && WS == 2, "slot counts assumed below");
+
+// LDS-only barrier (the loop hands data between waves through LDS alone, so
+// outstanding global loads of later planes need not complete).
+__device__ __forceinline__ void lds_barrier2()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__device__ __forceinline__ int xcd_remap2(int i, int n)
+{
+    const int q = n / kXcds2, r = n % kXcds2;
+    const int x = i % kXcds2, j = i / kXcds2;
+    return x * q + min(x, r) + j;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(NT) void twostep_kernel(TwoStepArgs a)
+{
+    __shared__ double Us[4 * USLOT];
+    __shared__ double Vs[4 * VSLOT];
+    __shared__ double red[NT / 64];
+
+    const int tid = threadIdx.x;
+    const int t = xcd_remap2(blockIdx.x, gridDim.x);
+    const int tx = t % a.ntx, ty = (t / a.ntx) % a.nty, tz = t / (a.ntx * a.nty);
+    const int ex = a.ex, ey = a.ey, ez = a.ez, pitch = a.pitch;
+    const int x0 = tx * TX, nxv = min(TX, ex - x0);
+    const int y0 = (int)((int64_t)ty * ey / a.nty), nyv = (int)((int64_t)(ty + 1) * ey / a.nty) - y0;
+    const int z0 = (int)((int64_t)tz * ez / a.ntz), nzv = (int)((int64_t)(tz + 1) * ez / a.ntz) - z0;
+    const int64_t ps = (int64_t)(ey + 2) * pitch;  // plane stride of the field, doubles
+
+    // u^t sources.  Cell (gx, gy) of the tile's two-cell ring, plane z:
+    //   inside the grid in x and y: the field, planes -1 .. ez (the ghost
+    //   planes hold the z faces);
+    //   one row outside in y: the field's ghost row, planes 0 .. ez-1;
+    //   one column outside in x: the x-halo array, planes 0 .. ez-1;
+    //   anything else is never an operand of a needed value and reads as 0.
+    const double *ub[US];
+    int64_t ust[US];
+    int uzl[US], uzh[US];
+#pragma unroll
+    for (int r = 0; r < US; ++r) {
+        const int i = tid + r * NT;
+        const int lx = i % UX, ly = i / UX;
+        const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
+        const bool in_tile = i < UP && lx < nxv + 4 && ly < nyv + 4;
+        const bool inx = gx >= 0 && gx < ex, iny = gy >= 0 && gy < ey;
+        ub[r] = a.cur;
+        ust[r] = 0;
+        uzl[r] = 1;
+        uzh[r] = 0;  // empty range: no load
+        if (in_tile) {
+            if (inx && (iny || gy == -1 || gy == ey)) {
+                ub[r] = a.cur + ps + (int64_t)(gy + 1) * pitch + gx;
+                ust[r] = ps;
+                uzl[r] = iny ? -1 : 0;
+                uzh[r] = iny ? ez : ez - 1;
+            } else if (iny && (gx == -1 || gx == ex)) {
+                ub[r] = a.xh + (gx < 0 ? 0 : (int64_t)ey * ez) + gy;
+                ust[r] = ey;
+                uzl[r] = 0;
+                uzh[r] = ez - 1;
+            }
+        }
+    }
+    auto load_plane = [&](int z, double (&dst)[US]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int r = 0; r < US; ++r) {
+            const bool ok = z >= uzl[r] && z <= uzh[r];
+            const double *p = ok ? ub[r] + (int64_t)z * ust[r] : a.cur;
+            const double v = __builtin_nontemporal_load(p);
+            dst[r] = ok ? v : 0.0;
+        }
+    };
+
+    // v cells: (vx, vy) of the one-cell ring region.  kind 1: inside the grid
+    // in x and y (computed inside the z range, Dirichlet on the z faces);
+    // kind 2: on an x or y face of the boundary layer (keeps its Dirichlet
+    // value inside the z range); kind 0: not needed.
+    int vc[VS], vkind[VS];
+#pragma unroll
+    for (int r = 0; r < VS; ++r) {
+        const int i = tid + r * NT;
+        const int vx = i % VX, vy = i / VX;
+        const bool in_tile = i < VP && vx < nxv + 2 && vy < nyv + 2;
+        const int gx = x0 - 1 + vx, gy = y0 - 1 + vy;
+        const bool inx = gx >= 0 && gx < ex, iny = gy >= 0 && gy < ey;
+        vc[r] = in_tile ? (vy + 1) * UX + vx + 1 : UX + 1;
+        vkind[r] = !in_tile ? 0 : (inx && iny) ? 1 : ((inx && (gy == -1 || gy == ey)) ||
+                                                     (iny && (gx == -1 || gx == ex))) ? 2 : 0;
+    }
+
+    // w cells: the tile; wc is the cell's index in the v region.
+    int wc[WS];
+    bool wok[WS];
+    int64_t wo[WS];
+#pragma unroll
+    for (int r = 0; r < WS; ++r) {
+        const int i = tid + r * NT;
+        const int wx = i % TX, wy = i / TX;
+        wok[r] = wx < nxv && wy < nyv;
+        wc[r] = (wy + 1) * VX + wx + 1;
+        wo[r] = (int64_t)(y0 + wy + 1) * pitch + x0 + wx;
+    }
+
+    // Step j writes u plane z0-2+j into LDS, computes v on plane z0-3+j and
+    // w on plane z0-5+j (whose v operands were all written before this step's
+    // barrier).  Four LDS slots per iterate keep every slot's last reader a
+    // barrier ahead of its next writer.
+    const int nsteps = nzv + 5;
+    double R[NB][US];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) load_plane(z0 - 2 + k, R[k]);
+    double rmax = 0.0;
+
+    auto step = [&](const int j, double (&Rk)[US]) __attribute__((always_inline)) {
+        double *Uw = Us + (j & 3) * USLOT;
+        if (j < nzv + 4) {
+#pragma unroll
+            for (int r = 0; r < US; ++r) Uw[tid + r * NT] = Rk[r];
+        }
+        load_plane(z0 - 2 + j + NB, Rk);
+        lds_barrier2();
+        const int zv = z0 - 3 + j;
+        if (j >= 2 && j <= nzv + 3) {
+            const double *Uc = Us + ((j - 1) & 3) * USLOT;
+            const double *Um = Us + ((j - 2) & 3) * USLOT;
+            const double *Up = Uw;
+            double *Vw = Vs + (j & 3) * VSLOT;
+            const bool inz = zv >= 0 && zv < ez;
+            const bool zface = zv == -1 || zv == ez;
+#pragma unroll
+            for (int r = 0; r < VS; ++r) {
+                const int c = vc[r];
+                double s = Uc[c];
+                s += Uc[c - 1];
+                s += Uc[c + 1];
+                s += Uc[c - UX];
+                s += Uc[c + UX];
+                s += Um[c];
+                s += Up[c];
+                const double keep = Uc[c];
+                const double v = (vkind[r] == 1 && inz) ? s * kW2
+                                 : ((vkind[r] == 1 && zface) || (vkind[r] == 2 && inz)) ? keep : 0.0;
+                Vw[tid + r * NT] = v;
+            }
+        }
+        if (j >= 5) {
+            const int zw = z0 - 5 + j;
+            const double *Vc = Vs + ((j - 2) & 3) * VSLOT;
+            const double *Vm = Vs + ((j - 3) & 3) * VSLOT;
+            const double *Vp = Vs + ((j - 1) & 3) * VSLOT;
+            double *outp = a.nxt + (int64_t)(zw + 1) * ps;
+#pragma unroll
+            for (int r = 0; r < WS; ++r) {
+                const int vi = wc[r];
+                double s = Vc[vi];
+                s += Vc[vi - 1];
+                s += Vc[vi + 1];
+                s += Vc[vi - VX];
+                s += Vc[vi + VX];
+                s += Vm[vi];
+                s += Vp[vi];
+                const double w = s * kW2;
+                if (wok[r]) __builtin_nontemporal_store(w, outp + wo[r]);
+                if (a.want_res && wok[r]) {
+                    const double d = fabs(w - Vc[vi]);
+                    rmax = d > rmax ? d : rmax;
+                }
+            }
+        }
+    };
+
+    for (int jb = 0; jb < nsteps; jb += NB) {
+        step(jb, R[0]);
+        if (jb + 1 < nsteps) step(jb + 1, R[1]);
+        if (jb + 2 < nsteps) step(jb + 2, R[2]);
+    }
+
+    if (a.want_res) {
+        double m = rmax;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double q = __shfl_xor(m, o);
+            m = q > m ? q : m;
+        }
+        if ((tid & 63) == 0) red[tid >> 6] = m;
+        __syncthreads();
+        if (tid == 0) {
+            double w = 0.0;
+            for (int i = 0; i < NT / 64; ++i) w = red[i] > w ? red[i] : w;
+            __hip_atomic_fetch_max(a.res, (unsigned long long)__double_as_longlong(w), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+int twostep_tiles(int ex, int ey, int ez, int zchunk, int *ntx, int *nty, int *ntz)
+{
+    *ntx = (ex + TX - 1) / TX;
+    *nty = (ey + TY - 1) / TY;
+    const int zc = zchunk > 0 && zchunk < ez ? zchunk : ez;
+    *ntz = (ez + zc - 1) / zc;
+    return *ntx * *nty * *ntz;
+}
+
+int launch_twostep(const TwoStepArgs &a, void *stream)
+{
+    const int grid = a.ntx * a.nty * a.ntz;
+    hipLaunchKernelGGL(twostep_kernel, dim3(grid), dim3(NT), 0, static_cast<hipStream_t>(stream), a);
+    return (int)hipGetLastError();
+}
+
+}  // namespace j3d

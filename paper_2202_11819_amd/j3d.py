@@ -51,7 +51,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EBUDGET", -4: "EBUSY",
 
 J3D_UNFUSED_BLOCK, J3D_UNFUSED_PHASE, J3D_FUSED, J3D_GRAPH = 0, 1, 2, 3
 MODES = {"unfused_block": 0, "unfused_phase": 1, "fused": 2, "graph": 3, "block_a": 4, "block_b": 5,
-         "block_c": 6, "host_staged": 7, "host_overlap": 8}
+         "block_c": 6, "host_staged": 7, "host_overlap": 8, "two_sweep": 9}
 J3D_CAPTURED = 16
 
 

@@ -251,6 +251,83 @@ def test_errors_leave_state_untouched(env):
 
 # ---- full-size workloads (the benchmark's launch configuration) ---------------
 
+@pytest.mark.parametrize("n, iters", [((64, 64, 64), 100), ((70, 37, 11), 9), ((130, 33, 9), 20),
+                                      ((5, 3, 2), 4), ((1, 1, 1), 7), ((17, 70, 5), 1), ((200, 130, 150), 12),
+                                      ((64, 48, 13), 0)])
+def test_two_sweep_matches_oracle(env, n, iters):
+    # two sweeps per launch on an undivided grid: ragged x tiles, y tiles of
+    # unequal rows, z chunks, odd counts (a fused sweep at the end), tiny grids
+    oracle, api, _ = env
+    check(oracle, api, n, bc=(0.25, -0.5, 1.0, 0.0, -0.75, 0.5), seed=6, iters=iters, mode="two_sweep")
+
+
+def test_two_sweep_faces_fixed_point_and_mode_mix(env):
+    oracle, api, j3d = env
+    # a linear field with per-cell faces stays fixed under two-sweep launches
+    n = (90, 20, 18)
+    i, j, k = (np.arange(v + 2, dtype=np.float64) for v in n)
+    full = 0.5 + 0.25 * i[None, None, :] - 0.125 * j[None, :, None] + 2.0 * k[:, None, None]
+    u0 = np.ascontiguousarray(full[1:-1, 1:-1, 1:-1])
+    faces = [full[1:-1, 1:-1, 0], full[1:-1, 1:-1, -1], full[1:-1, 0, 1:-1], full[1:-1, -1, 1:-1],
+             full[0, 1:-1, 1:-1], full[-1, 1:-1, 1:-1]]
+    with api.Solver(n) as s:
+        s.set_interior(u0)
+        for f in range(6):
+            s.set_face(f, faces[f])
+        assert s.run(24, mode="two_sweep", residual=True) == 0.0
+        assert np.array_equal(s.get_interior(), u0)
+    # random per-cell faces, two-sweep runs interleaved with the other modes
+    rng = np.random.default_rng(5)
+    n = (77, 41, 29)
+    nx, ny, nz = n
+    faces = [rng.uniform(-1, 1, (nz, ny)), rng.uniform(-1, 1, (nz, ny)), rng.uniform(-1, 1, (nz, nx)),
+             rng.uniform(-1, 1, (nz, nx)), rng.uniform(-1, 1, (ny, nx)), rng.uniform(-1, 1, (ny, nx))]
+    want, want_r, _ = oracle.jacobi(n, 40, seed=8, faces=faces, nthreads=NTH)
+    with api.Solver(n, seed=8) as s:
+        for f in range(6):
+            s.set_face(f, faces[f])
+        s.run(5, mode="fused")
+        s.run(8, mode="two_sweep")
+        s.run(3, mode="graph")
+        s.run(7, mode="two_sweep")
+        s.run(2, mode="unfused_block")
+        r = s.run(15, mode="two_sweep", residual=True)
+        assert s.iters_done() == 40
+        assert np.array_equal(s.get_interior(), want) and r == want_r
+
+
+def test_two_sweep_refuses_decomposed_and_captured(env):
+    oracle, api, j3d = env
+    n = (32, 30, 28)
+    want, _, _ = oracle.jacobi(n, 4, seed=3, nthreads=NTH)
+    with api.Solver(n, nblk=(2, 1, 1), seed=3) as s:
+        with pytest.raises(j3d.J3DError) as e:
+            s.run(4, mode="two_sweep")
+        assert e.value.status == j3d.J3D_EINVAL
+        assert s.iters_done() == 0
+        s.run(4, mode="graph")
+        assert np.array_equal(s.get_interior(), want)
+    with api.Solver(n, seed=3) as s:
+        with pytest.raises(j3d.J3DError) as e:
+            s.run(4, mode="two_sweep+graph")
+        assert e.value.status == j3d.J3D_EINVAL
+        s.run(4, mode="two_sweep")
+        assert np.array_equal(s.get_interior(), want)
+
+
+@pytest.mark.slow
+def test_two_sweep_512_full_run_matches_oracle(env):
+    # the 512^3 grid undivided, 1000 sweeps in 500 two-sweep launches
+    oracle, api, _ = env
+    n = (512, 512, 512)
+    with api.Solver(n, seed=1) as s:
+        r = s.run(1000, mode="two_sweep", residual=True)
+        got = s.get_interior()
+    want, want_r, _ = oracle.jacobi(n, 1000, seed=1, nthreads=NTH)
+    assert r == want_r
+    assert np.array_equal(got, want), f"max |diff| {np.abs(got - want).max()}"
+
+
 def test_overdecomposed_512_sampled_cells(env):
     # 512^3 as 8^3 blocks of 64^3: the benchmark's grid and launch shape.  A
     # cell's value after t sweeps depends only on cells within t steps, so the
