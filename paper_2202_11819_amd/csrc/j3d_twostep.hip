@@ -28,17 +28,25 @@ namespace {
 constexpr double kW2 = 1.0 / 7.0;  // fl(1/7)
 constexpr int kXcds2 = 8;          // XCDs per MI355X
 
-constexpr int TX = 64, TY = 16, NT = 512;
-constexpr int UX = TX + 4, UY = TY + 4, UP = UX * UY;  // u^t: tile with a two-cell ring
-constexpr int VX = TX + 2, VY = TY + 2, VP = VX * VY;  // v: tile with a one-cell ring
-constexpr int US = (UP + NT - 1) / NT;                 // u cells per thread and plane
-constexpr int VS = (VP + NT - 1) / NT;                 // v cells per thread and plane
-constexpr int WS = TX * TY / NT;                       // w cells per thread and plane
-constexpr int USLOT = US * NT;                         // LDS doubles per u plane (every lane writes)
-constexpr int VSLOT = VS * NT;
-constexpr int NB = 3;                                  // planes of u held in registers per lane
-static_assert(TX * TY % NT == 0, "whole w rows per thread");
-static_assert(US == 3 && VS == 3 && WS == 2, "slot counts assumed below");
+constexpr int TX = 64;  // tile width: one 64-lane wave per row of w
+constexpr int NB = 3;   // planes of u held in registers per lane
+
+// Tile shapes: TX x TY cells of w, NT threads.  u^t covers the tile with a
+// two-cell ring, v the tile with a one-cell ring; each LDS plane ends in one
+// sink cell that takes the writes of lanes past the region.
+template <int TY_, int NT_>
+struct Shape {
+    static constexpr int TY = TY_, NT = NT_;
+    static constexpr int UX = TX + 4, UY = TY + 4, UP = UX * UY;
+    static constexpr int VX = TX + 2, VY = TY + 2, VP = VX * VY;
+    static constexpr int US = (UP + NT - 1) / NT;  // u cells per thread and plane
+    static constexpr int VS = (VP + NT - 1) / NT;  // v cells per thread and plane
+    static constexpr int WS = TX * TY / NT;        // w cells per thread and plane
+    static constexpr int USLOT = UP + 2, VSLOT = VP + 2;
+    static_assert(TX * TY % NT == 0, "whole w rows per thread");
+    static_assert(US == 3 && VS == 3 && WS == 2, "slot counts assumed below");
+    static_assert((USLOT + VSLOT) * 4 * 8 <= 160 * 1024 - 1024, "LDS of one workgroup");
+};
 
 // LDS-only barrier (the loop hands data between waves through LDS alone, so
 // outstanding global loads of later planes need not complete).
@@ -58,8 +66,11 @@ __device__ __forceinline__ int xcd_remap2(int i, int n)
 
 }  // namespace
 
-__global__ __launch_bounds__(NT) void twostep_kernel(TwoStepArgs a)
+template <class S>
+__global__ __launch_bounds__(S::NT) void twostep_kernel(TwoStepArgs a)
 {
+    constexpr int TY = S::TY, NT = S::NT, UX = S::UX, UP = S::UP, VX = S::VX, VP = S::VP;
+    constexpr int US = S::US, VS = S::VS, WS = S::WS, USLOT = S::USLOT, VSLOT = S::VSLOT;
     __shared__ double Us[4 * USLOT];
     __shared__ double Vs[4 * VSLOT];
     __shared__ double red[NT / 64];
@@ -161,7 +172,7 @@ __global__ __launch_bounds__(NT) void twostep_kernel(TwoStepArgs a)
         double *Uw = Us + (j & 3) * USLOT;
         if (j < nzv + 4) {
 #pragma unroll
-            for (int r = 0; r < US; ++r) Uw[tid + r * NT] = Rk[r];
+            for (int r = 0; r < US; ++r) Uw[min(tid + r * NT, UP)] = Rk[r];
         }
         load_plane(z0 - 2 + j + NB, Rk);
         lds_barrier2();
@@ -186,7 +197,7 @@ __global__ __launch_bounds__(NT) void twostep_kernel(TwoStepArgs a)
                 const double keep = Uc[c];
                 const double v = (vkind[r] == 1 && inz) ? s * kW2
                                  : ((vkind[r] == 1 && zface) || (vkind[r] == 2 && inz)) ? keep : 0.0;
-                Vw[tid + r * NT] = v;
+                Vw[min(tid + r * NT, VP)] = v;
             }
         }
         if (j >= 5) {
@@ -239,10 +250,15 @@ __global__ __launch_bounds__(NT) void twostep_kernel(TwoStepArgs a)
     }
 }
 
-int twostep_tiles(int ex, int ey, int ez, int zchunk, int *ntx, int *nty, int *ntz)
+using Shape16 = Shape<16, 512>;   // 64 x 16 tiles, two workgroups per compute unit
+using Shape32 = Shape<32, 1024>;  // 64 x 32 tiles, one workgroup per compute unit
+
+int twostep_tile_rows(int shape) { return shape == 1 ? Shape32::TY : Shape16::TY; }
+
+int twostep_tiles(int shape, int ex, int ey, int ez, int zchunk, int *ntx, int *nty, int *ntz)
 {
     *ntx = (ex + TX - 1) / TX;
-    *nty = (ey + TY - 1) / TY;
+    *nty = (ey + twostep_tile_rows(shape) - 1) / twostep_tile_rows(shape);
     const int zc = zchunk > 0 && zchunk < ez ? zchunk : ez;
     *ntz = (ez + zc - 1) / zc;
     return *ntx * *nty * *ntz;
@@ -251,7 +267,12 @@ int twostep_tiles(int ex, int ey, int ez, int zchunk, int *ntx, int *nty, int *n
 int launch_twostep(const TwoStepArgs &a, void *stream)
 {
     const int grid = a.ntx * a.nty * a.ntz;
-    hipLaunchKernelGGL(twostep_kernel, dim3(grid), dim3(NT), 0, static_cast<hipStream_t>(stream), a);
+    if (a.shape == 1)
+        hipLaunchKernelGGL(twostep_kernel<Shape32>, dim3(grid), dim3(Shape32::NT), 0,
+                           static_cast<hipStream_t>(stream), a);
+    else
+        hipLaunchKernelGGL(twostep_kernel<Shape16>, dim3(grid), dim3(Shape16::NT), 0,
+                           static_cast<hipStream_t>(stream), a);
     return (int)hipGetLastError();
 }
 
