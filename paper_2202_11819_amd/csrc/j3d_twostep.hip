@@ -118,12 +118,16 @@ __global__ __launch_bounds__(S::NT) void twostep_kernel(TwoStepArgs a)
             }
         }
     }
+    // Plain (temporal) loads: the ring cells of a tile are the edge cells of
+    // its neighbours, which run at about the same planes; a non-temporal hint
+    // evicts those lines before the neighbour reads them (measured 1.53x
+    // instead of 1.15x the algorithmic read bytes, 517 instead of 598 GLUP/s).
     auto load_plane = [&](int z, double (&dst)[US]) __attribute__((always_inline)) {
 #pragma unroll
         for (int r = 0; r < US; ++r) {
             const bool ok = z >= uzl[r] && z <= uzh[r];
             const double *p = ok ? ub[r] + (int64_t)z * ust[r] : a.cur;
-            const double v = __builtin_nontemporal_load(p);
+            const double v = *p;
             dst[r] = ok ? v : 0.0;
         }
     };
