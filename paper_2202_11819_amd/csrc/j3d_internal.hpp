@@ -135,8 +135,7 @@ constexpr int flat_x0(int ex, int tnx, int tx)
 
 // Two sweeps per launch on a grid of one block (j3d_twostep.hip).  The
 // launch reads iterate t from `cur` and writes iterate t+2 to `nxt`; x-y tiles
-// of 64 x 16 (shape 0, 512 threads) or 64 x 32 cells (shape 1, 1024 threads),
-// z cut into ntz near-equal pieces.
+// of 64 x 16 cells (512 threads), z cut into ntz near-equal pieces.
 struct TwoStepArgs {
     const double *cur;        // field of iterate t (plane index 0: the z- ghost plane)
     double *nxt;              // field that receives iterate t+2
@@ -145,10 +144,9 @@ struct TwoStepArgs {
     int32_t ex, ey, ez, pitch;
     int32_t ntx, nty, ntz;
     int32_t want_res;
-    int32_t shape;
 };
-// Tile counts for a shape, block and z-chunk (0 or >= ez: whole planes); returns the total.
-int twostep_tiles(int shape, int ex, int ey, int ez, int zchunk, int *ntx, int *nty, int *ntz);
+// Tile counts for a block and z-chunk (0 or >= ez: whole planes); returns the total.
+int twostep_tiles(int ex, int ey, int ez, int zchunk, int *ntx, int *nty, int *ntz);
 int launch_twostep(const TwoStepArgs &a, void *stream);
 
 // ---- launchers (defined in j3d_kernels.hip); all enqueue on `stream` ----------

@@ -583,12 +583,6 @@ j3d_status one_sweep(j3d_solver *s, int mode, int p, bool res, int slot, hipStre
     return set_error(J3D_EINVAL, "unknown mode %d", mode);
 }
 
-// Tile shape of the two-sweep kernel (0: 64 x 16 x 512 threads, 1: 64 x 32 x 1024).
-#ifndef J3D_TWOSTEP_SHAPE
-#define J3D_TWOSTEP_SHAPE 0
-#endif
-constexpr int kTwoStepShape = J3D_TWOSTEP_SHAPE;
-
 // TWO_SWEEP: iters / 2 launches of the two-sweep kernel (each reads the
 // current buffer and writes the other), then one fused sweep if iters is
 // odd.  The residual comes from the launch that performs the last sweep.
@@ -603,17 +597,16 @@ j3d_status run_two_sweep(j3d_solver *s, int64_t iters, bool want_res, unsigned l
     a.ez = B.ext[2];
     a.pitch = B.pitch;
     a.res = res;
-    a.shape = kTwoStepShape;
     // whole planes when the x-y tiles alone give every compute unit two
     // workgroups, else z-chunks (at least 4 planes) for about that many
     int ntx = 0, nty = 0, ntz = 0;
-    twostep_tiles(a.shape, a.ex, a.ey, a.ez, 0, &ntx, &nty, &ntz);
+    twostep_tiles(a.ex, a.ey, a.ez, 0, &ntx, &nty, &ntz);
     int zc = 0;
     if (ntx * nty < 2 * s->cus) {
         const int want = (2 * s->cus + ntx * nty - 1) / (ntx * nty);
         zc = std::max(4, (a.ez + want - 1) / want);
     }
-    twostep_tiles(a.shape, a.ex, a.ey, a.ez, zc, &a.ntx, &a.nty, &a.ntz);
+    twostep_tiles(a.ex, a.ey, a.ez, zc, &a.ntx, &a.nty, &a.ntz);
     int p = s->parity;
     const int64_t pairs = iters / 2;
     for (int64_t k = 0; k < pairs; ++k) {
