@@ -206,6 +206,8 @@ def bench_overdecomposed(args):
     s.close()
     del u0
     torch.cuda.empty_cache()
+    if not args.no_two_sweep:
+        out["undivided_two_sweep"] = two_sweep_side(n, sweeps)
     if not args.no_copy:
         out["copy_GBps"] = round(copy_bandwidth(), 1)
         out["roofline"]["frac_of_copy"] = round(achieved / out["copy_GBps"], 4)
@@ -213,6 +215,32 @@ def bench_overdecomposed(args):
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def two_sweep_side(n, sweeps):
+    """The same grid left undivided, one sweep per launch (graph) against two
+    (TWO_SWEEP): a side measurement, not the benchmark's value."""
+    import torch
+    from paper_2202_11819_amd import api
+
+    cells = n[0] * n[1] * n[2]
+    sweeps -= sweeps % 2
+    res = {"grid": list(n), "blocks": [1, 1, 1], "sweeps": sweeps}
+    with api.Solver(n, seed=1) as s:
+        for mode, key in (("graph", "one_sweep_GLUPs"), ("two_sweep", "two_sweep_GLUPs")):
+            s.run(10, mode=mode)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            s.run(sweeps, mode=mode)
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            res[key] = round(cells * sweeps / ms / 1e6, 2)
+            if mode == "two_sweep":
+                res["two_sweep_launch_ms"] = round(2 * ms / sweeps, 4)
+    torch.cuda.empty_cache()
+    return res
 
 
 def bench_modes(args):
@@ -389,6 +417,7 @@ def main():
     ap.add_argument("--tune", default="", help="variant,zchunk,blocks_per_cu")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--no-two-sweep", action="store_true", help="skip the undivided two-sweep side measurement")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--requests", type=int, default=1100, help="serve workload: number of requests")
     ap.add_argument("--serve-dump", default="", help="serve workload: write per-request records here")
