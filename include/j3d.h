@@ -96,11 +96,12 @@ typedef enum {
  *                 on its tile plus a one-cell ring in LDS and writes only
  *                 every second iterate, halving the HBM traffic per
  *                 iteration.  An odd count ends with one FUSED sweep.  EINVAL
- *                 for a decomposed grid or with CAPTURED.  Not in the paper;
- *                 it applies where no block boundary needs an exchange.
+ *                 for a decomposed grid.  Not in the paper; it applies where
+ *                 no block boundary needs an exchange.
  *  CAPTURED:      a flag OR-ed with any mode: its iterations are captured once
- *                 into HIP graphs (50 sweeps per graph for FUSED, 2 for the
- *                 others, whose graphs hold thousands of nodes) and replayed;
+ *                 into HIP graphs (50 sweeps per graph for FUSED, 48 for
+ *                 TWO_SWEEP, 2 for the others, whose graphs hold thousands of
+ *                 nodes) and replayed;
  *                 GRAPH is FUSED | CAPTURED.  Results never depend on the mode. */
 typedef enum {
     J3D_UNFUSED_BLOCK = 0,

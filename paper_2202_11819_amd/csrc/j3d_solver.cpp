@@ -283,10 +283,11 @@ j3d_status sweep_tiles(j3d_solver *s, int parity, bool fused, bool res, int32_t 
     return hip_status(launch_sweep(s->tune.variant, a, cnt, st), "sweep launch");
 }
 
-// Sweeps per HIP graph: an even number, so a replay returns to the same
-// buffer parity.  A fused sweep is one node; the per-block modes put
-// thousands of nodes into one sweep, so their graphs hold two.
-int graph_sweeps(int mode) { return mode == J3D_FUSED ? 50 : 2; }
+// Launches per HIP graph (one_sweep calls; a TWO_SWEEP launch performs two
+// sweeps): an even number, so a replay returns to the same buffer parity.  A
+// fused sweep is one node; the per-block modes put thousands of nodes into
+// one sweep, so their graphs hold two.
+int graph_sweeps(int mode) { return mode == J3D_FUSED ? 50 : mode == J3D_TWO_SWEEP ? 24 : 2; }
 
 // Modes whose sweep is one launch that may use the persistent schedule.
 bool persistent_mode(const j3d_solver *s, int mode)
@@ -556,6 +557,35 @@ j3d_status run_host_staged(j3d_solver *s, int p, bool res, bool overlap, hipStre
     return sweep_tiles(s, p, false, res, 0, s->ntiles, main);
 }
 
+// One launch of the two-sweep kernel: iterate in buffer p -> two sweeps later
+// in buffer p^1.  Whole planes when the x-y tiles alone give every compute
+// unit two workgroups, else z-chunks (at least 4 planes) for about that many.
+j3d_status two_sweep_launch(j3d_solver *s, int p, bool res, hipStream_t st)
+{
+    const BlockDesc &B = s->plan.blocks[0];
+    double *base = reinterpret_cast<double *>(s->arena);
+    TwoStepArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.ex = B.ext[0];
+    a.ey = B.ext[1];
+    a.ez = B.ext[2];
+    a.pitch = B.pitch;
+    a.res = reinterpret_cast<unsigned long long *>(s->arena + s->plan.off_res);
+    int ntx = 0, nty = 0, ntz = 0;
+    twostep_tiles(a.ex, a.ey, a.ez, 0, &ntx, &nty, &ntz);
+    int zc = 0;
+    if (ntx * nty < 2 * s->cus) {
+        const int want = (2 * s->cus + ntx * nty - 1) / (ntx * nty);
+        zc = std::max(4, (a.ez + want - 1) / want);
+    }
+    twostep_tiles(a.ex, a.ey, a.ez, zc, &a.ntx, &a.nty, &a.ntz);
+    a.cur = base + B.off[p];
+    a.nxt = base + B.off[p ^ 1];
+    a.xh = base + B.xoff[p];
+    a.want_res = res ? 1 : 0;
+    return hip_status(launch_twostep(a, st), "two-sweep launch");
+}
+
 // One sweep of `mode` reading parity p, enqueued on st.
 j3d_status one_sweep(j3d_solver *s, int mode, int p, bool res, int slot, hipStream_t st)
 {
@@ -579,54 +609,10 @@ j3d_status one_sweep(j3d_solver *s, int mode, int p, bool res, int slot, hipStre
     case J3D_HOST_OVERLAP:
         // the overlapped update's shell pass carries no residual
         return run_host_staged(s, p, res, !res, st);
+    case J3D_TWO_SWEEP:  // one launch, two sweeps
+        return two_sweep_launch(s, p, res, st);
     }
     return set_error(J3D_EINVAL, "unknown mode %d", mode);
-}
-
-// TWO_SWEEP: iters / 2 launches of the two-sweep kernel (each reads the
-// current buffer and writes the other), then one fused sweep if iters is
-// odd.  The residual comes from the launch that performs the last sweep.
-j3d_status run_two_sweep(j3d_solver *s, int64_t iters, bool want_res, unsigned long long *res)
-{
-    const BlockDesc &B = s->plan.blocks[0];
-    double *base = reinterpret_cast<double *>(s->arena);
-    TwoStepArgs a;
-    std::memset(&a, 0, sizeof a);
-    a.ex = B.ext[0];
-    a.ey = B.ext[1];
-    a.ez = B.ext[2];
-    a.pitch = B.pitch;
-    a.res = res;
-    // whole planes when the x-y tiles alone give every compute unit two
-    // workgroups, else z-chunks (at least 4 planes) for about that many
-    int ntx = 0, nty = 0, ntz = 0;
-    twostep_tiles(a.ex, a.ey, a.ez, 0, &ntx, &nty, &ntz);
-    int zc = 0;
-    if (ntx * nty < 2 * s->cus) {
-        const int want = (2 * s->cus + ntx * nty - 1) / (ntx * nty);
-        zc = std::max(4, (a.ez + want - 1) / want);
-    }
-    twostep_tiles(a.ex, a.ey, a.ez, zc, &a.ntx, &a.nty, &a.ntz);
-    int p = s->parity;
-    const int64_t pairs = iters / 2;
-    for (int64_t k = 0; k < pairs; ++k) {
-        a.cur = base + B.off[p];
-        a.nxt = base + B.off[p ^ 1];
-        a.xh = base + B.xoff[p];
-        a.want_res = want_res && (iters & 1) == 0 && k + 1 == pairs;
-        j3d_status st = hip_status(launch_twostep(a, s->stream), "two-sweep launch");
-        if (st != J3D_OK) return st;
-        p ^= 1;
-    }
-    if (iters & 1) {
-        const int slot = persistent_mode(s, J3D_FUSED) ? (int)(s->persist_launches++ & 1) : 0;
-        j3d_status st = one_sweep(s, J3D_FUSED, p, want_res, slot, s->stream);
-        if (st != J3D_OK) return st;
-        p ^= 1;
-    }
-    s->parity = p;
-    s->iters_done += iters;
-    return J3D_OK;
 }
 
 // Read back a requested residual (synchronises) after a run.
@@ -641,6 +627,43 @@ j3d_status finish_run(j3d_solver *s, double *residual_out, const unsigned long l
     double r;
     std::memcpy(&r, &bits, sizeof r);
     *residual_out = r;
+    return J3D_OK;
+}
+
+// TWO_SWEEP: iters / 2 two-sweep launches (each reads the current buffer and
+// writes the other), replayed from HIP graphs of 24 launches when captured,
+// then one fused sweep if iters is odd.  The residual comes from the launch
+// that performs the last sweep, which is never inside a graph.
+j3d_status run_two_sweep(j3d_solver *s, int64_t iters, bool want_res, bool captured)
+{
+    int p = s->parity;
+    const int64_t pairs = iters / 2;
+    const bool res_in_pair = want_res && (iters & 1) == 0;
+    int64_t k = 0;
+    if (captured) {
+        const int g = graph_sweeps(J3D_TWO_SWEEP);
+        const int64_t plain = pairs - (res_in_pair ? 1 : 0);
+        for (; k + g <= plain; k += g) {
+            hipGraphExec_t exec = nullptr;
+            j3d_status st = get_graph(s, J3D_TWO_SWEEP, p, 0, &exec);
+            if (st != J3D_OK) return st;
+            st = hip_status(hipGraphLaunch(exec, s->stream), "graph launch");
+            if (st != J3D_OK) return st;
+        }
+    }
+    for (; k < pairs; ++k) {
+        j3d_status st = two_sweep_launch(s, p, res_in_pair && k + 1 == pairs, s->stream);
+        if (st != J3D_OK) return st;
+        p ^= 1;
+    }
+    if (iters & 1) {
+        const int slot = persistent_mode(s, J3D_FUSED) ? (int)(s->persist_launches++ & 1) : 0;
+        j3d_status st = one_sweep(s, J3D_FUSED, p, want_res, slot, s->stream);
+        if (st != J3D_OK) return st;
+        p ^= 1;
+    }
+    s->parity = p;
+    s->iters_done += iters;
     return J3D_OK;
 }
 
@@ -766,7 +789,6 @@ j3d_status j3d_run(j3d_solver *s, int64_t iters, j3d_mode mode_in, double *resid
     if (mode < J3D_UNFUSED_BLOCK || mode > J3D_TWO_SWEEP)
         return set_error(J3D_EINVAL, "unknown mode %d", (int)mode_in);
     if (mode == J3D_TWO_SWEEP) {
-        if (captured) return set_error(J3D_EINVAL, "the two-sweep mode is not captured into graphs");
         if (s->plan.blocks.size() != 1)
             return set_error(J3D_EINVAL, "the two-sweep mode needs a grid of one block (%zu blocks)",
                              s->plan.blocks.size());
@@ -783,7 +805,7 @@ j3d_status j3d_run(j3d_solver *s, int64_t iters, j3d_mode mode_in, double *resid
             st = hip_status(launch_fill_u64(res, 1, 0ull, s->stream), "residual reset");
             if (st != J3D_OK) return st;
         }
-        st = run_two_sweep(s, iters, want_res, res);
+        st = run_two_sweep(s, iters, want_res, captured);
         if (st != J3D_OK) return st;
         return finish_run(s, residual_out, res);
     }

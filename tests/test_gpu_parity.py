@@ -296,23 +296,35 @@ def test_two_sweep_faces_fixed_point_and_mode_mix(env):
         assert np.array_equal(s.get_interior(), want) and r == want_r
 
 
-def test_two_sweep_refuses_decomposed_and_captured(env):
+def test_two_sweep_refuses_decomposed_grid(env):
     oracle, api, j3d = env
     n = (32, 30, 28)
     want, _, _ = oracle.jacobi(n, 4, seed=3, nthreads=NTH)
     with api.Solver(n, nblk=(2, 1, 1), seed=3) as s:
-        with pytest.raises(j3d.J3DError) as e:
-            s.run(4, mode="two_sweep")
-        assert e.value.status == j3d.J3D_EINVAL
+        for mode in ("two_sweep", "two_sweep+graph"):
+            with pytest.raises(j3d.J3DError) as e:
+                s.run(4, mode=mode)
+            assert e.value.status == j3d.J3D_EINVAL
         assert s.iters_done() == 0
         s.run(4, mode="graph")
         assert np.array_equal(s.get_interior(), want)
-    with api.Solver(n, seed=3) as s:
-        with pytest.raises(j3d.J3DError) as e:
-            s.run(4, mode="two_sweep+graph")
-        assert e.value.status == j3d.J3D_EINVAL
-        s.run(4, mode="two_sweep")
-        assert np.array_equal(s.get_interior(), want)
+
+
+def test_two_sweep_graphs_replay_exactly(env):
+    # graphs of 24 two-sweep launches, replayed several times with eager work
+    # and host synchronisation between the replays; every stage against the oracle
+    oracle, api, _ = env
+    n, bc = (70, 37, 50), (0.5, -0.25, 0.0, 1.0, -1.0, 0.75)
+    with api.Solver(n, bc=bc, seed=12) as s:
+        done = 0
+        for k, (it, mode) in enumerate([(100, "two_sweep+graph"), (3, "fused"), (97, "two_sweep+graph"),
+                                        (50, "graph"), (151, "two_sweep+graph")]):
+            r = s.run(it, mode=mode, residual=True)
+            done += it
+            want, want_r, _ = oracle.jacobi(n, done, bc=bc, seed=12, nthreads=NTH)
+            assert np.array_equal(s.get_interior(), want), (k, mode, done)
+            assert r == want_r, (k, mode, done)
+        assert s.iters_done() == done
 
 
 @pytest.mark.slow
