@@ -252,6 +252,17 @@ j3d_status j3d_batch_create(int32_t count, const j3d_problem *probs, const int64
  * synchronises.  A batch runs once; ESTATE afterwards.                       */
 j3d_status j3d_batch_run(j3d_batch *b, double *residuals_out);
 
+/* The same run with two sweeps per launch (the TWO_SWEEP scheme of j3d_run)
+ * for batches whose problems are all undivided (one block each; EINVAL
+ * otherwise, before any device work): problems with an odd count first take
+ * one ordinary sweep in one launch over the batch, then launch k covers the
+ * problems with more than k sweep pairs left, each advancing two sweeps.
+ * Results and residuals are bit-identical to j3d_batch_run.  The batch's
+ * tile shape from j3d_tune is used for the odd sweep only; the two-sweep
+ * launches use 64 x 16 tiles and z-chunks of 32.  Not in the paper.  A batch
+ * runs once, by either call; ESTATE afterwards.                              */
+j3d_status j3d_batch_run_two_sweep(j3d_batch *b, double *residuals_out);
+
 /* Copy problem i's interior to dst (dense).  Synchronises for host dst. */
 j3d_status j3d_batch_get_interior(j3d_batch *b, int32_t i, double *dst, int dst_on_device);
 

@@ -93,7 +93,9 @@ class Batch:
         self.h = C.j3d_batch_create(self.problems, self.iters, self.arena.data_ptr(), self.arena_bytes,
                                     self.stream.cuda_stream, tune)
 
-    def run(self, residuals=True):
+    def run(self, residuals=True, two_sweep=False):
+        if two_sweep:
+            return C.j3d_batch_run_two_sweep(self.h, len(self.problems), residuals)
         return C.j3d_batch_run(self.h, len(self.problems), residuals)
 
     def get_interior(self, i) -> np.ndarray:

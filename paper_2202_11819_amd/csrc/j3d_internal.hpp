@@ -26,6 +26,7 @@
 #pragma once
 
 #include <cstdint>
+#include <vector>
 
 #include "../../include/j3d.h"
 
@@ -133,20 +134,33 @@ constexpr int flat_x0(int ex, int tnx, int tx)
     return tx == 0 ? 0 : tx >= tnx ? ex : (int)(((int64_t)tx * ex / tnx) & ~(int64_t)15);
 }
 
-// Two sweeps per launch on a grid of one block (j3d_twostep.hip).  The
-// launch reads iterate t from `cur` and writes iterate t+2 to `nxt`; x-y tiles
-// of 64 x 16 cells (512 threads), z cut into ntz near-equal pieces.
+// Two sweeps per launch on grids of one block (j3d_twostep.hip).  A launch
+// reads iterate t from one buffer and writes iterate t+2 to the other; x-y
+// tiles of 64 x 16 cells (512 threads), z cut into near-equal pieces.
+// Single grid: blocks == nullptr, the fields below `blocks` are unused.
+// Multi-problem (batched) launch: tile_count tiles from tiles[tile_begin..];
+// a tile's problem takes part while step < limit, reading buffer
+// (base + step) & 1, and adds its residual when step + 1 == limit (ProbDesc
+// counts launches here, not sweeps).
 struct TwoStepArgs {
     const double *cur;        // field of iterate t (plane index 0: the z- ghost plane)
     double *nxt;              // field that receives iterate t+2
     const double *xh;         // x-halo arrays (x- then x+, ey*ez each, y fastest)
-    unsigned long long *res;  // residual word of the second sweep (bit pattern)
+    unsigned long long *res;  // residual word(s) of the second sweep (bit pattern)
     int32_t ex, ey, ez, pitch;
     int32_t ntx, nty, ntz;
     int32_t want_res;
+    const BlockDesc *blocks;  // multi-problem launch only
+    const ProbDesc *probs;
+    const Tile *tiles;
+    double *base;
+    int64_t step;
+    int32_t tile_begin, tile_count, zchunk;
 };
 // Tile counts for a block and z-chunk (0 or >= ez: whole planes); returns the total.
 int twostep_tiles(int ex, int ey, int ez, int zchunk, int *ntx, int *nty, int *ntz);
+// Tiles of blocks b0..b1-1 for a multi-problem launch with z-chunks of zchunk planes.
+void twostep_make_tiles(const BlockDesc *blocks, int32_t b0, int32_t b1, int zchunk, std::vector<Tile> *tiles);
 int launch_twostep(const TwoStepArgs &a, void *stream);
 
 // ---- launchers (defined in j3d_kernels.hip); all enqueue on `stream` ----------

@@ -902,6 +902,7 @@ struct j3d_batch {
     int64_t max_iters = 0;
     bool ran = false;
     uint32_t persist_launches = 0;
+    std::vector<int> final_parity;      // buffer holding each problem's result after the run
 };
 
 extern "C" {
@@ -1012,6 +1013,127 @@ j3d_status j3d_batch_run(j3d_batch *b, double *residuals_out)
         if (st != J3D_OK) return st;
     }
     b->ran = true;
+    b->final_parity.resize(count);
+    for (int32_t i = 0; i < count; ++i) b->final_parity[i] = (int)(b->plan.probs[i].iters & 1);
+    if (residuals_out) {
+        std::vector<unsigned long long> bits(count);
+        st = hip_status(hipMemcpyAsync(bits.data(), res, count * sizeof(unsigned long long),
+                                       hipMemcpyDeviceToHost, b->stream),
+                        "residual readback");
+        if (st == J3D_OK) st = hip_status(hipStreamSynchronize(b->stream), "residual readback");
+        if (st != J3D_OK) return st;
+        for (int32_t i = 0; i < count; ++i) std::memcpy(&residuals_out[i], &bits[i], sizeof(double));
+    }
+    return J3D_OK;
+}
+
+j3d_status j3d_batch_run_two_sweep(j3d_batch *b, double *residuals_out)
+{
+    if (!b) return set_error(J3D_EINVAL, "batch is NULL");
+    if (b->ran) return set_error(J3D_ESTATE, "batch already ran");
+    const int32_t count = (int32_t)b->plan.probs.size();
+    for (int32_t i = 0; i < count; ++i)
+        if (b->plan.probs[i].nblocks != 1)
+            return set_error(J3D_EINVAL, "two sweeps per launch need undivided problems (problem %d has %d blocks)",
+                             i, b->plan.probs[i].nblocks);
+    // two-sweep tiles: problems by pair count, longest first, so the tiles
+    // active at pair step s are a prefix of the table
+    constexpr int kZchunk = 32;
+    std::vector<int32_t> order(count);
+    for (int32_t i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return b->plan.probs[x].iters / 2 > b->plan.probs[y].iters / 2;
+    });
+    std::vector<Tile> tiles2;
+    std::vector<int32_t> prefix2(1, 0);
+    for (int32_t k = 0; k < count; ++k) {
+        const ProbPlan &pp = b->plan.probs[order[k]];
+        twostep_make_tiles(b->plan.blocks.data(), pp.block_begin, pp.block_begin + 1, kZchunk, &tiles2);
+        prefix2.push_back((int32_t)tiles2.size());
+    }
+    if (tiles2.size() > b->plan.tiles_cap)
+        return set_error(J3D_EINVAL, "two-sweep tiles (%zu) exceed the tile table (%llu)", tiles2.size(),
+                         (unsigned long long)b->plan.tiles_cap);
+
+    unsigned long long *res = reinterpret_cast<unsigned long long *>(b->arena + b->plan.off_res);
+    ProbDesc *probs_dev = reinterpret_cast<ProbDesc *>(b->arena + b->plan.off_probs);
+    j3d_status st = hip_status(launch_fill_u64(res, count, 0ull, b->stream), "residual reset");
+    if (st != J3D_OK) return st;
+    auto upload_probs = [&](const std::vector<ProbDesc> &pd) {
+        j3d_status r = hip_status(hipMemcpyAsync(probs_dev, pd.data(), pd.size() * sizeof(ProbDesc),
+                                                 hipMemcpyHostToDevice, b->stream),
+                                  "problem table");
+        return r == J3D_OK ? hip_status(hipStreamSynchronize(b->stream), "problem table") : r;
+    };
+    std::vector<ProbDesc> pd(count);
+    // an odd count starts with one ordinary sweep (residual only if it is the last)
+    bool any_odd = false;
+    for (int32_t i = 0; i < count; ++i) {
+        std::memset(&pd[i], 0, sizeof(ProbDesc));
+        const int64_t it = b->plan.probs[i].iters;
+        pd[i].limit = it & 1;
+        pd[i].res_slot = i;
+        pd[i].flags = it == 1 ? PF_RES_LAST : 0;
+        any_odd = any_odd || (it & 1);
+    }
+    if (any_odd) {
+        st = upload_probs(pd);
+        if (st != J3D_OK) return st;
+        SweepArgs a;
+        std::memset(&a, 0, sizeof a);
+        a.base = reinterpret_cast<double *>(b->arena);
+        a.blocks = reinterpret_cast<const BlockDesc *>(b->arena + b->plan.off_blocks);
+        a.probs = probs_dev;
+        a.tiles = reinterpret_cast<const Tile *>(b->arena + b->plan.off_tiles);
+        a.res = res;
+        a.queue = reinterpret_cast<unsigned int *>(b->arena + b->plan.off_queue);
+        a.zchunk = b->zchunk;
+        a.step = 0;
+        a.tile_count = b->prefix_tiles[count];
+        a.flags = SW_FUSED | SW_MULTI;
+        int grid = a.tile_count;
+        if (b->tune.blocks_per_cu > 0) {
+            a.flags |= SW_PERSIST;
+            a.queue_slot = (int)(b->persist_launches++ & 1);
+            grid = std::min(grid, b->cus * b->tune.blocks_per_cu);
+        }
+        st = hip_status(launch_sweep(b->tune.variant, a, grid, b->stream), "batch sweep launch");
+        if (st != J3D_OK) return st;
+    }
+    // then iters / 2 two-sweep launches per problem
+    for (int32_t i = 0; i < count; ++i) {
+        const int64_t it = b->plan.probs[i].iters;
+        pd[i].base = it & 1;
+        pd[i].limit = it / 2;
+        pd[i].flags = 0;
+    }
+    st = upload_probs(pd);
+    if (st == J3D_OK) st = upload_tiles(b->plan, tiles2, b->arena, b->stream);
+    if (st != J3D_OK) return st;
+    TwoStepArgs a2;
+    std::memset(&a2, 0, sizeof a2);
+    a2.base = reinterpret_cast<double *>(b->arena);
+    a2.blocks = reinterpret_cast<const BlockDesc *>(b->arena + b->plan.off_blocks);
+    a2.probs = probs_dev;
+    a2.tiles = reinterpret_cast<const Tile *>(b->arena + b->plan.off_tiles);
+    a2.res = res;
+    a2.zchunk = kZchunk;
+    int32_t active = count;
+    const int64_t max_pairs = count > 0 ? b->plan.probs[order[0]].iters / 2 : 0;
+    for (int64_t s2 = 0; s2 < max_pairs; ++s2) {
+        while (active > 0 && b->plan.probs[order[active - 1]].iters / 2 <= s2) --active;
+        a2.step = s2;
+        a2.tile_begin = 0;
+        a2.tile_count = prefix2[active];
+        st = hip_status(launch_twostep(a2, b->stream), "two-sweep batch launch");
+        if (st != J3D_OK) return st;
+    }
+    b->ran = true;
+    b->final_parity.resize(count);
+    for (int32_t i = 0; i < count; ++i) {
+        const int64_t it = b->plan.probs[i].iters;
+        b->final_parity[i] = (int)(((it & 1) + it / 2) & 1);
+    }
     if (residuals_out) {
         std::vector<unsigned long long> bits(count);
         st = hip_status(hipMemcpyAsync(bits.data(), res, count * sizeof(unsigned long long),
@@ -1028,7 +1150,7 @@ j3d_status j3d_batch_get_interior(j3d_batch *b, int32_t i, double *dst, int dst_
 {
     if (!b || !dst) return set_error(J3D_EINVAL, "NULL argument");
     if (i < 0 || i >= (int32_t)b->plan.probs.size()) return set_error(J3D_EINVAL, "problem %d out of range", i);
-    const int parity = b->ran ? (int)(b->plan.probs[i].iters & 1) : 0;
+    const int parity = b->ran ? b->final_parity[i] : 0;
     return copy_dense(b->plan, b->arena, i, parity, dst, dst_on_device, true, b->stream);
 }
 

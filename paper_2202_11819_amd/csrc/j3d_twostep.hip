@@ -77,11 +77,52 @@ __global__ __launch_bounds__(S::NT) void twostep_kernel(TwoStepArgs a)
 
     const int tid = threadIdx.x;
     const int t = xcd_remap2(blockIdx.x, gridDim.x);
-    const int tx = t % a.ntx, ty = (t / a.ntx) % a.nty, tz = t / (a.ntx * a.nty);
-    const int ex = a.ex, ey = a.ey, ez = a.ez, pitch = a.pitch;
+    // Tile geometry and buffers: the launch's single grid, or (multi-problem
+    // launch) the tile's block and problem from the tables.
+    const double *cur, *xh;
+    double *nxt;
+    unsigned long long *resp;
+    int ex, ey, ez, pitch, tx, ty, tz, nty, ntz;
+    bool want_res;
+    if (a.blocks) {
+        const Tile tl = a.tiles[a.tile_begin + t];
+        const BlockDesc *__restrict__ B = a.blocks + tl.block;
+        const ProbDesc *__restrict__ P = a.probs + B->prob;
+        if (a.step >= P->limit) return;  // uniform over the workgroup: no barrier reached
+        const int p = (int)((P->base + a.step) & 1);
+        ex = B->ext[0];
+        ey = B->ext[1];
+        ez = B->ext[2];
+        pitch = B->pitch;
+        cur = a.base + B->off[p];
+        nxt = a.base + B->off[p ^ 1];
+        xh = a.base + B->xoff[p];
+        resp = a.res + P->res_slot;
+        want_res = a.step + 1 == P->limit;
+        tx = tl.tx;
+        ty = tl.ty;
+        tz = tl.tz;
+        nty = (ey + TY - 1) / TY;
+        ntz = (ez + a.zchunk - 1) / a.zchunk;
+    } else {
+        ex = a.ex;
+        ey = a.ey;
+        ez = a.ez;
+        pitch = a.pitch;
+        cur = a.cur;
+        nxt = a.nxt;
+        xh = a.xh;
+        resp = a.res;
+        want_res = a.want_res != 0;
+        tx = t % a.ntx;
+        ty = (t / a.ntx) % a.nty;
+        tz = t / (a.ntx * a.nty);
+        nty = a.nty;
+        ntz = a.ntz;
+    }
     const int x0 = tx * TX, nxv = min(TX, ex - x0);
-    const int y0 = (int)((int64_t)ty * ey / a.nty), nyv = (int)((int64_t)(ty + 1) * ey / a.nty) - y0;
-    const int z0 = (int)((int64_t)tz * ez / a.ntz), nzv = (int)((int64_t)(tz + 1) * ez / a.ntz) - z0;
+    const int y0 = (int)((int64_t)ty * ey / nty), nyv = (int)((int64_t)(ty + 1) * ey / nty) - y0;
+    const int z0 = (int)((int64_t)tz * ez / ntz), nzv = (int)((int64_t)(tz + 1) * ez / ntz) - z0;
     const int64_t ps = (int64_t)(ey + 2) * pitch;  // plane stride of the field, doubles
 
     // u^t sources.  Cell (gx, gy) of the tile's two-cell ring, plane z:
@@ -100,18 +141,18 @@ __global__ __launch_bounds__(S::NT) void twostep_kernel(TwoStepArgs a)
         const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
         const bool in_tile = i < UP && lx < nxv + 4 && ly < nyv + 4;
         const bool inx = gx >= 0 && gx < ex, iny = gy >= 0 && gy < ey;
-        ub[r] = a.cur;
+        ub[r] = cur;
         ust[r] = 0;
         uzl[r] = 1;
         uzh[r] = 0;  // empty range: no load
         if (in_tile) {
             if (inx && (iny || gy == -1 || gy == ey)) {
-                ub[r] = a.cur + ps + (int64_t)(gy + 1) * pitch + gx;
+                ub[r] = cur + ps + (int64_t)(gy + 1) * pitch + gx;
                 ust[r] = ps;
                 uzl[r] = iny ? -1 : 0;
                 uzh[r] = iny ? ez : ez - 1;
             } else if (iny && (gx == -1 || gx == ex)) {
-                ub[r] = a.xh + (gx < 0 ? 0 : (int64_t)ey * ez) + gy;
+                ub[r] = xh + (gx < 0 ? 0 : (int64_t)ey * ez) + gy;
                 ust[r] = ey;
                 uzl[r] = 0;
                 uzh[r] = ez - 1;
@@ -126,7 +167,7 @@ __global__ __launch_bounds__(S::NT) void twostep_kernel(TwoStepArgs a)
 #pragma unroll
         for (int r = 0; r < US; ++r) {
             const bool ok = z >= uzl[r] && z <= uzh[r];
-            const double *p = ok ? ub[r] + (int64_t)z * ust[r] : a.cur;
+            const double *p = ok ? ub[r] + (int64_t)z * ust[r] : cur;
             const double v = *p;
             dst[r] = ok ? v : 0.0;
         }
@@ -209,7 +250,7 @@ __global__ __launch_bounds__(S::NT) void twostep_kernel(TwoStepArgs a)
             const double *Vc = Vs + ((j - 2) & 3) * VSLOT;
             const double *Vm = Vs + ((j - 3) & 3) * VSLOT;
             const double *Vp = Vs + ((j - 1) & 3) * VSLOT;
-            double *outp = a.nxt + (int64_t)(zw + 1) * ps;
+            double *outp = nxt + (int64_t)(zw + 1) * ps;
 #pragma unroll
             for (int r = 0; r < WS; ++r) {
                 const int vi = wc[r];
@@ -222,7 +263,7 @@ __global__ __launch_bounds__(S::NT) void twostep_kernel(TwoStepArgs a)
                 s += Vp[vi];
                 const double w = s * kW2;
                 if (wok[r]) __builtin_nontemporal_store(w, outp + wo[r]);
-                if (a.want_res && wok[r]) {
+                if (want_res && wok[r]) {
                     const double d = fabs(w - Vc[vi]);
                     rmax = d > rmax ? d : rmax;
                 }
@@ -236,7 +277,7 @@ __global__ __launch_bounds__(S::NT) void twostep_kernel(TwoStepArgs a)
         if (jb + 2 < nsteps) step(jb + 2, R[2]);
     }
 
-    if (a.want_res) {
+    if (want_res) {
         double m = rmax;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
@@ -248,7 +289,7 @@ __global__ __launch_bounds__(S::NT) void twostep_kernel(TwoStepArgs a)
         if (tid == 0) {
             double w = 0.0;
             for (int i = 0; i < NT / 64; ++i) w = red[i] > w ? red[i] : w;
-            __hip_atomic_fetch_max(a.res, (unsigned long long)__double_as_longlong(w), __ATOMIC_RELAXED,
+            __hip_atomic_fetch_max(resp, (unsigned long long)__double_as_longlong(w), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         }
     }
@@ -267,9 +308,20 @@ int twostep_tiles(int ex, int ey, int ez, int zchunk, int *ntx, int *nty, int *n
     return *ntx * *nty * *ntz;
 }
 
+void twostep_make_tiles(const BlockDesc *blocks, int32_t b0, int32_t b1, int zchunk, std::vector<Tile> *tiles)
+{
+    for (int32_t b = b0; b < b1; ++b) {
+        int ntx = 0, nty = 0, ntz = 0;
+        twostep_tiles(blocks[b].ext[0], blocks[b].ext[1], blocks[b].ext[2], zchunk, &ntx, &nty, &ntz);
+        for (int tz = 0; tz < ntz; ++tz)
+            for (int ty = 0; ty < nty; ++ty)
+                for (int tx = 0; tx < ntx; ++tx) tiles->push_back(Tile{b, tx, ty, tz});
+    }
+}
+
 int launch_twostep(const TwoStepArgs &a, void *stream)
 {
-    const int grid = a.ntx * a.nty * a.ntz;
+    const int grid = a.blocks ? a.tile_count : a.ntx * a.nty * a.ntz;
     hipLaunchKernelGGL(twostep_kernel<Tile16>, dim3(grid), dim3(Tile16::NT), 0, static_cast<hipStream_t>(stream),
                        a);
     return (int)hipGetLastError();

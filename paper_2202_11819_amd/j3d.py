@@ -105,6 +105,7 @@ _SIGS = {
     "j3d_batch_create": ([c_int32, _P, POINTER(c_int64), c_void_p, c_uint64, c_void_p,
                           POINTER(j3d_tune), POINTER(_H)], c_int),
     "j3d_batch_run": ([_H, _DP], c_int),
+    "j3d_batch_run_two_sweep": ([_H, _DP], c_int),
     "j3d_batch_get_interior": ([_H, c_int32, c_void_p, c_int], c_int),
     "j3d_batch_destroy": ([_H], c_int),
     "j3d_pool_request_bytes": ([_P, POINTER(c_uint64)], c_int),
@@ -311,6 +312,15 @@ def j3d_batch_run(h, count: int, want_residuals: bool = True):
         _check(_lib.j3d_batch_run(h, r), "j3d_batch_run")
         return np.array(list(r))
     _check(_lib.j3d_batch_run(h, None), "j3d_batch_run")
+    return None
+
+
+def j3d_batch_run_two_sweep(h, count: int, want_residuals: bool = True):
+    if want_residuals:
+        r = (c_double * count)()
+        _check(_lib.j3d_batch_run_two_sweep(h, r), "j3d_batch_run_two_sweep")
+        return np.array(list(r))
+    _check(_lib.j3d_batch_run_two_sweep(h, None), "j3d_batch_run_two_sweep")
     return None
 
 

@@ -211,12 +211,12 @@ def bench_batch(args):
     tune = tune_batch(problems, iters, log=_log, force=getattr(args, "retune", False))
     _log(f"[batch] tune {tune} ({j3d.variants()[tune[0]]})")
 
-    def timed_batch(t):
+    def timed_batch(t, two_sweep=False):
         b = Batch(problems, iters, tune=t)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        b.run(residuals=False)
+        b.run(residuals=False, two_sweep=two_sweep)
         e1.record()
         e1.synchronize()
         b.close()
@@ -225,6 +225,9 @@ def bench_batch(args):
     timed_batch(tune)
     tb = min(timed_batch(tune) for _ in range(2))
     tdef = timed_batch(None)
+    # the same batch with two sweeps per launch (all problems are undivided)
+    timed_batch(tune, True)
+    t2 = min(timed_batch(tune, True) for _ in range(2))
     # per-problem loop: each problem solved on its own with the plain solver
     run_s = 0.0
     wall0 = time.perf_counter()
@@ -242,6 +245,7 @@ def bench_batch(args):
     out = {"metric": "batched FP64 Jacobi3D GLUP/s (256 problems, one launch per sweep)",
            "value": round(lups / tb / 1e9, 2), "unit": "GLUP/s", "higher_is_better": True,
            "batched_s": round(tb, 4), "batched_default_tune_s": round(tdef, 4),
+           "two_sweep_batched_s": round(t2, 4), "two_sweep_GLUPs": round(lups / t2 / 1e9, 2),
            "per_problem_loop_s": round(run_s, 4), "per_problem_loop_GLUPs": round(lups / run_s / 1e9, 2),
            "per_problem_loop_wall_s": round(wall, 2), "speedup_vs_loop": round(run_s / tb, 3),
            "tune": list(tune), "tile": list(j3d.variants()[tune[0]]),

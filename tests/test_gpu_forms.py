@@ -64,6 +64,37 @@ def test_batch_matches_oracle(env, tune):
             assert res[i] == want_r, i
 
 
+def test_batch_two_sweep_matches_oracle(env):
+    # two sweeps per launch over the batch: odd counts take one ordinary sweep
+    # first; counts 0, 1, 2, 3 and ragged, non-cubic, tiny and z-chunked sizes
+    oracle, api, j3d, W = env
+    rng = np.random.default_rng(21)
+    specs = []
+    for i, it in enumerate([0, 1, 2, 3, 17, 40, 41, 8, 1, 29, 64, 5]):
+        n = tuple(int(v) for v in rng.integers(3, 140, 3)) if i % 4 else (1 + i, 2, 70)
+        bc = tuple(float(v) for v in rng.uniform(-1, 1, 6))
+        specs.append(W.Spec(n=n, bc=bc, seed=9, pid=i, iters=it))
+    with api.Batch([_problem(api, s) for s in specs], [s.iters for s in specs]) as b:
+        res = b.run(two_sweep=True)
+        for i, s in enumerate(specs):
+            want, want_r, _ = oracle.jacobi(s.n, s.iters, bc=s.bc, seed=s.seed, pid=s.pid, nthreads=NTH)
+            assert np.array_equal(b.get_interior(i), want), (i, s.n, s.iters)
+            assert res[i] == want_r, i
+        with pytest.raises(j3d.J3DError) as e:
+            b.run(two_sweep=True)
+        assert e.value.status == j3d.J3D_ESTATE
+
+
+def test_batch_two_sweep_refuses_decomposed_problems(env):
+    _, api, j3d, W = env
+    specs = [W.Spec(n=(20, 20, 20), iters=4), W.Spec(n=(20, 20, 20), nblk=(2, 1, 1), iters=4, pid=1)]
+    with api.Batch([_problem(api, s) for s in specs], [s.iters for s in specs]) as b:
+        with pytest.raises(j3d.J3DError) as e:
+            b.run(two_sweep=True)
+        assert e.value.status == j3d.J3D_EINVAL
+        b.run()  # the batch is untouched and still runs once
+
+
 def test_batch_run_twice_is_refused(env):
     _, api, j3d, W = env
     specs = _mix(W, count=3)
@@ -253,6 +284,19 @@ def test_pool_zero_iterations_returns_initial_grid(env):
 
 
 # ---- the batched and served workloads at their own sizes -----------------------
+
+@pytest.mark.slow
+def test_batch_two_sweep_full_workload_matches_oracle(env):
+    # all 256 problems of the batched benchmark, two sweeps per launch
+    oracle, api, j3d, W = env
+    specs = W.batch()
+    with api.Batch([_problem(api, s) for s in specs], [s.iters for s in specs]) as b:
+        res = b.run(two_sweep=True)
+        for i, s in enumerate(specs):
+            want, want_r, _ = oracle.jacobi(s.n, s.iters, bc=s.bc, seed=s.seed, pid=s.pid, nthreads=NTH)
+            assert res[i] == want_r, i
+            assert np.array_equal(b.get_interior(i), want), i
+
 
 @pytest.mark.slow
 def test_batch_full_workload_matches_oracle(env):
