@@ -427,6 +427,7 @@ def main():
                     help="serve workload: stop a request at the first residual check with r <= tol (0: never)")
     ap.add_argument("--fill-cells", type=int, default=-1, help="serve workload: pool round policy (-1: default)")
     ap.add_argument("--pool-tune", default="", help="serve workload: variant,zchunk of the pool's rounds")
+    ap.add_argument("--pool-two-sweep", action="store_true", help="serve workload: two sweeps per launch in the pool")
     ap.add_argument("--backlog-share", type=int, default=-1,
                     help="serve workload: rounds hold at least 1/k of the running cells (-1: default)")
     ap.add_argument("--odf-edge", type=int, default=256, help="odf workload: grid edge")

@@ -313,6 +313,14 @@ j3d_status j3d_pool_set_policy(j3d_pool *pl, int64_t fill_cells, int32_t max_wai
  * tile count is checked against the pool's tile table at admission).       */
 j3d_status j3d_pool_set_tune(j3d_pool *pl, const j3d_tune *t);
 
+/* enable 1: rounds advance requests two sweeps per launch (the TWO_SWEEP
+ * scheme of j3d_run; every request is an undivided grid): a request whose
+ * share of the round is odd takes one ordinary sweep first.  Results,
+ * residuals and check points are unchanged (bit-identical).  enable 0: one
+ * sweep per launch (the default).  Only while the pool is empty (ESTATE
+ * otherwise); EINVAL for other values.  Not in the paper.                  */
+j3d_status j3d_pool_set_two_sweep(j3d_pool *pl, int32_t enable);
+
 /* Non-blocking progress: retires a completed round (updating every request's
  * sweep count and residual, deciding which finished), starts the result
  * copies of finished requests, and reports in done[] (at most cap) the slots

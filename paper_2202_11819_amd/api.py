@@ -149,6 +149,10 @@ class Pool:
         """Tile shape of the rounds; only while no request is admitted."""
         C.j3d_pool_set_tune(self.h, variant, zchunk)
 
+    def set_two_sweep(self, enable=True):
+        """Two sweeps per launch in the rounds; only while no request is admitted."""
+        C.j3d_pool_set_two_sweep(self.h, enable)
+
     def poll(self):
         return C.j3d_pool_poll(self.h, self.max_slots)
 

@@ -39,6 +39,7 @@ struct Req {
     double tol = 0.0, residual = 0.0;
     int32_t check_every = 0;
     int32_t waited = 0;  // consecutive rounds this request was left out of
+    int buf = 0;         // field buffer holding the current iterate
     double *host_result = nullptr;
     hipEvent_t gather_ev = nullptr, copy_ev = nullptr;
 };
@@ -47,6 +48,7 @@ struct RoundEntry {
     int32_t slot;
     uint32_t gen;
     int64_t base, limit;
+    int newbuf;  // buffer of the iterate after the round
 };
 
 struct Layout {
@@ -119,6 +121,11 @@ struct j3d_pool {
     int64_t fill_cells = int64_t(1) << 25;
     int32_t max_wait = 32;
     int32_t backlog_share = 2;  // > 0: the target is at least 1/backlog_share of the running cells
+    // two sweeps per launch: tables of the pair launches (page-locked, apart
+    // from the single-sweep ones, which are still in flight when these are filled)
+    bool two_sweep = false;
+    ProbDesc *host_probs2 = nullptr;
+    Tile *host_tiles2 = nullptr;
 };
 
 namespace {
@@ -175,7 +182,7 @@ SweepArgs pool_args(j3d_pool *pl)
 j3d_status start_copy(j3d_pool *pl, int32_t slot)
 {
     Req &r = pl->reqs[slot];
-    const int p = (int)(r.iters_done & 1);
+    const int p = r.buf;
     double *dst = reinterpret_cast<double *>(pl->arena) + r.blk.off[p ^ 1];
     j3d_status st = hip_status(
         launch_gather_block(reinterpret_cast<double *>(pl->arena),
@@ -288,10 +295,14 @@ j3d_status j3d_pool_admit(j3d_pool *pl, const j3d_problem *p, int64_t max_iters,
     int64_t ntx, nty;
     tiles_xy(vi, d.n[0], d.n[1], &ntx, &nty);
     const int64_t tiles = ntx * nty * ((d.n[2] + pl->zchunk - 1) / pl->zchunk);
-    if (tiles > kPoolTilesPerReq)
+    int tx2 = 0, ty2 = 0, tz2 = 0;
+    const int64_t tiles2 = pl->two_sweep ? twostep_tiles((int)d.n[0], (int)d.n[1], (int)d.n[2], kPoolZchunk, &tx2,
+                                                         &ty2, &tz2)
+                                         : 0;
+    if (tiles > kPoolTilesPerReq || tiles2 > kPoolTilesPerReq)
         return set_error(J3D_EINVAL, "request of %lldx%lldx%lld needs %lld tiles, more than %lld",
-                         (long long)d.n[0], (long long)d.n[1], (long long)d.n[2], (long long)tiles,
-                         (long long)kPoolTilesPerReq);
+                         (long long)d.n[0], (long long)d.n[1], (long long)d.n[2],
+                         (long long)std::max(tiles, tiles2), (long long)kPoolTilesPerReq);
     int32_t s = -1;
     for (int32_t i = 0; i < pl->max_slots; ++i)
         if (pl->reqs[i].state == R_FREE) {
@@ -324,6 +335,7 @@ j3d_status j3d_pool_admit(j3d_pool *pl, const j3d_problem *p, int64_t max_iters,
     r.blk.prob = s;
     r.blk.face_total = 2 * (d.n[1] * d.n[2] + d.n[0] * d.n[2] + d.n[0] * d.n[1]);
     r.iters_done = 0;
+    r.buf = 0;
     r.max_iters = max_iters;
     r.tol = tol;
     r.check_every = check_every;
@@ -401,19 +413,47 @@ j3d_status j3d_pool_step(j3d_pool *pl, int32_t sweeps)
         Req &r = pl->reqs[c.slot];
         r.waited = chosen[c.slot] ? 0 : r.waited + 1;
     }
+    // Per chosen request: k sweeps this round (up to its next residual check).
+    // One sweep per launch: step j advances every request with j < k.  Two
+    // sweeps per launch: a request with odd k first takes one ordinary sweep
+    // (one launch for the round), then k / 2 two-sweep launches; descriptors
+    // then carry buffer parities instead of sweep counts.
+    std::vector<Tile> tiles2;
+    bool any_odd = false;
+    int64_t max_pairs = 0;
     for (int32_t s = 0; s < pl->max_slots; ++s) {
         Req &r = pl->reqs[s];
         if (r.state != R_RUNNING || !chosen[s]) continue;
         const int64_t base = r.iters_done;
         int64_t limit = r.max_iters;
         if (r.check_every > 0) limit = std::min(limit, (base / r.check_every + 1) * r.check_every);
+        const int64_t k = std::max<int64_t>(0, std::min<int64_t>(sweeps, limit - base));
         ProbDesc &pd = pl->host_probs[s];
         std::memset(&pd, 0, sizeof pd);
-        pd.base = base;
-        pd.limit = limit;
         pd.res_slot = s;
-        pd.flags = PF_RES_LAST;
-        pl->round.push_back(RoundEntry{s, r.gen, base, limit});
+        int newbuf;
+        if (!pl->two_sweep) {
+            pd.base = base;
+            pd.limit = limit;
+            pd.flags = PF_RES_LAST;
+            newbuf = (int)((base + k) & 1);
+        } else {
+            pd.base = r.buf;
+            pd.limit = r.buf + (k & 1);
+            pd.flags = k == 1 ? PF_RES_LAST : 0;
+            ProbDesc &q = pl->host_probs2[s];
+            std::memset(&q, 0, sizeof q);
+            q.base = r.buf ^ (int)(k & 1);
+            q.limit = k / 2;
+            q.res_slot = s;
+            newbuf = r.buf ^ (int)(k & 1) ^ (int)((k / 2) & 1);
+            any_odd = any_odd || (k & 1) != 0;
+            max_pairs = std::max<int64_t>(max_pairs, k / 2);
+            const size_t at = tiles2.size();
+            twostep_make_tiles(&r.blk, 0, 1, kPoolZchunk, &tiles2);
+            for (size_t i = at; i < tiles2.size(); ++i) tiles2[i].block = s;
+        }
+        pl->round.push_back(RoundEntry{s, r.gen, base, limit, newbuf});
         Plan one;
         one.blocks.assign(1, r.blk);
         std::vector<Tile> t;
@@ -435,9 +475,35 @@ j3d_status j3d_pool_step(j3d_pool *pl, int32_t sweeps)
     SweepArgs a = pool_args(pl);
     a.tile_begin = 0;
     a.tile_count = (int32_t)tiles.size();
-    for (int32_t j = 0; j < sweeps && st == J3D_OK; ++j) {
+    const int32_t one_sweep_launches = pl->two_sweep ? (any_odd ? 1 : 0) : sweeps;
+    for (int32_t j = 0; j < one_sweep_launches && st == J3D_OK; ++j) {
         a.step = j;
         st = hip_status(launch_sweep(pl->variant, a, a.tile_count, pl->stream), "round sweep");
+    }
+    if (st == J3D_OK && max_pairs > 0) {
+        // the pair launches' tables replace the single sweep's, in stream order
+        std::memcpy(pl->host_tiles2, tiles2.data(), tiles2.size() * sizeof(Tile));
+        st = hip_status(hipMemcpyAsync(pl->arena + pl->lay.off_probs, pl->host_probs2,
+                                       pl->max_slots * sizeof(ProbDesc), hipMemcpyHostToDevice, pl->stream),
+                        "round upload");
+        if (st == J3D_OK)
+            st = hip_status(hipMemcpyAsync(pl->arena + pl->lay.off_tiles, pl->host_tiles2,
+                                           tiles2.size() * sizeof(Tile), hipMemcpyHostToDevice, pl->stream),
+                            "round upload");
+        TwoStepArgs a2;
+        std::memset(&a2, 0, sizeof a2);
+        a2.base = reinterpret_cast<double *>(pl->arena);
+        a2.blocks = reinterpret_cast<const BlockDesc *>(pl->arena + pl->lay.off_blocks);
+        a2.probs = reinterpret_cast<const ProbDesc *>(pl->arena + pl->lay.off_probs);
+        a2.tiles = reinterpret_cast<const Tile *>(pl->arena + pl->lay.off_tiles);
+        a2.res = res;
+        a2.zchunk = kPoolZchunk;
+        a2.tile_begin = 0;
+        a2.tile_count = (int32_t)tiles2.size();
+        for (int64_t s2 = 0; s2 < max_pairs && st == J3D_OK; ++s2) {
+            a2.step = s2;
+            st = hip_status(launch_twostep(a2, pl->stream), "round two-sweep launch");
+        }
     }
     if (st == J3D_OK)
         st = hip_status(hipMemcpyAsync(pl->host_res, res, pl->max_slots * sizeof(unsigned long long),
@@ -461,6 +527,7 @@ j3d_status j3d_pool_poll(j3d_pool *pl, int32_t *done, int32_t cap, int32_t *n_do
                 if (r.state != R_RUNNING || r.gen != e.gen) continue;  // released meanwhile
                 const int64_t adv = std::min<int64_t>(pl->round_sweeps, e.limit - e.base);
                 r.iters_done = e.base + adv;
+                r.buf = e.newbuf;
                 if (r.iters_done == e.limit) {
                     double v;
                     std::memcpy(&v, &pl->host_res[e.slot], sizeof v);
@@ -544,6 +611,30 @@ j3d_status j3d_pool_set_tune(j3d_pool *pl, const j3d_tune *t)
     return J3D_OK;
 }
 
+j3d_status j3d_pool_set_two_sweep(j3d_pool *pl, int32_t enable)
+{
+    if (!pl) return set_error(J3D_EINVAL, "pool is NULL");
+    if (enable != 0 && enable != 1) return set_error(J3D_EINVAL, "enable %d is not 0 or 1", enable);
+    for (const Req &r : pl->reqs)
+        if (r.state != R_FREE)
+            return set_error(J3D_ESTATE, "sweeps per launch can change only while the pool is empty");
+    if (enable && !pl->host_probs2) {
+        j3d_status st = hip_status(hipHostMalloc((void **)&pl->host_probs2, pl->max_slots * sizeof(ProbDesc), 0),
+                                   "pinned table");
+        if (st != J3D_OK) return st;
+        st = hip_status(hipHostMalloc((void **)&pl->host_tiles2,
+                                      (size_t)pl->max_slots * kPoolTilesPerReq * sizeof(Tile), 0),
+                        "pinned table");
+        if (st != J3D_OK) {
+            (void)hipHostFree(pl->host_probs2);
+            pl->host_probs2 = nullptr;
+            return st;
+        }
+    }
+    pl->two_sweep = enable != 0;
+    return J3D_OK;
+}
+
 j3d_status j3d_pool_release(j3d_pool *pl, int32_t slot)
 {
     if (!pl) return set_error(J3D_EINVAL, "pool is NULL");
@@ -588,6 +679,8 @@ j3d_status j3d_pool_destroy(j3d_pool *pl)
     if (pl->host_probs) (void)hipHostFree(pl->host_probs);
     if (pl->host_blocks) (void)hipHostFree(pl->host_blocks);
     if (pl->host_tiles) (void)hipHostFree(pl->host_tiles);
+    if (pl->host_probs2) (void)hipHostFree(pl->host_probs2);
+    if (pl->host_tiles2) (void)hipHostFree(pl->host_tiles2);
     delete pl;
     return st;
 }

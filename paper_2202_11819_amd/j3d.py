@@ -115,6 +115,7 @@ _SIGS = {
     "j3d_pool_step": ([_H, c_int32], c_int),
     "j3d_pool_set_policy": ([_H, c_int64, c_int32, c_int32], c_int),
     "j3d_pool_set_tune": ([_H, POINTER(j3d_tune)], c_int),
+    "j3d_pool_set_two_sweep": ([_H, c_int32], c_int),
     "j3d_pool_poll": ([_H, POINTER(c_int32), c_int32, POINTER(c_int32), POINTER(c_int32)], c_int),
     "j3d_pool_result": ([_H, c_int32, _DP, POINTER(c_int64)], c_int),
     "j3d_pool_release": ([_H, c_int32], c_int),
@@ -386,6 +387,10 @@ def j3d_pool_set_tune(h, variant=-1, zchunk=32, default=False):
 def j3d_pool_set_policy(h, fill_cells: int, max_wait_rounds: int = 32, backlog_share: int = 0):
     _check(_lib.j3d_pool_set_policy(h, int(fill_cells), int(max_wait_rounds), int(backlog_share)),
            "j3d_pool_set_policy")
+
+
+def j3d_pool_set_two_sweep(h, enable: bool):
+    _check(_lib.j3d_pool_set_two_sweep(h, 1 if enable else 0), "j3d_pool_set_two_sweep")
 
 
 def j3d_pool_poll(h, cap: int = 1024):

@@ -38,11 +38,13 @@ def nearest_rank(values, q):
 
 
 def serve_pool(trace, budget_bytes, max_slots=256, round_sweeps=50, check_every=50, tol=0.0,
-               keep_results=False, log=None, fill_cells=None, tune=None, backlog_share=None):
+               keep_results=False, log=None, fill_cells=None, tune=None, backlog_share=None, two_sweep=False):
     """Serve `trace` (list of workloads.Request) in real time; per-request records.
     fill_cells, backlog_share: round policy, tune: (variant, zchunk) of the
-    rounds (None keeps the library defaults)."""
+    rounds (None keeps the library defaults), two_sweep: two sweeps per launch."""
     pool = Pool(budget_bytes, max_slots=max_slots)
+    if two_sweep:
+        pool.set_two_sweep(True)
     if fill_cells is not None or backlog_share is not None:
         pool.set_policy(1 << 25 if fill_cells is None else fill_cells, 32, 2 if backlog_share is None else backlog_share)
     if tune is not None:
@@ -170,8 +172,9 @@ def bench_serve(args):
     ptune = getattr(args, "pool_tune", "")
     ptune = tuple(int(v) for v in ptune.split(",")) if ptune else None
     tol = float(getattr(args, "tol", 0.0) or 0.0)
+    two = bool(getattr(args, "pool_two_sweep", False))
     recs, rounds = serve_pool(trace, budget, log=_log, fill_cells=None if fill < 0 else fill, tune=ptune,
-                              backlog_share=None if share < 0 else share, tol=tol)
+                              backlog_share=None if share < 0 else share, tol=tol, two_sweep=two)
     pool_sum = summarize(recs, warmup)
     srecs = serve_serial(trace, log=_log, tol=tol)
     serial_sum = summarize(srecs, warmup)
@@ -191,7 +194,7 @@ def bench_serve(args):
            "pool": pool_sum, "serial_plain": serial_sum, "rounds": rounds, "fill_cells": fill,
            "mix_vs_alone": {"requests": len(recs), "residual_bit_identical": same_res,
                             "sweeps_identical": same_it, "stopped_early": early},
-           "backlog_share": share,
+           "backlog_share": share, "pool_two_sweep": two,
            "pool_tune": list(ptune) if ptune else None,
            "config": {"workload": f"{count} Jacobi3D solve requests, Poisson arrivals at {rate:.2f}/s "
                                   f"({load} x serial capacity), per-axis size U{{32..384}}, 50..2000 sweeps, "

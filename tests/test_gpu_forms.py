@@ -139,15 +139,18 @@ def _flat_variant(j3d):
     return [i for i, v in enumerate(j3d.variants()) if v[0] == 0][0]
 
 
-@pytest.mark.parametrize("tune", [None, "flat", (8, 16)])
+@pytest.mark.parametrize("tune", [None, "flat", (8, 16), "two_sweep"])
 def test_pool_requests_match_oracle_and_solo_runs(env, tune):
     oracle, api, j3d, W = env
     from paper_2202_11819_amd import serve
+    two = tune == "two_sweep"
+    if two:
+        tune = None
     if tune == "flat":
         tune = (_flat_variant(j3d), 64)
     trace = _requests(W)
     recs, rounds = serve.serve_pool(trace, budget_bytes=2 << 30, max_slots=8, round_sweeps=50,
-                                    check_every=50, keep_results=True, tune=tune)
+                                    check_every=50, keep_results=True, tune=tune, two_sweep=two)
     assert rounds > 1
     for r, req in zip(recs, trace):
         s = req.spec
@@ -158,12 +161,13 @@ def test_pool_requests_match_oracle_and_solo_runs(env, tune):
     # alone in a pool of its own: the same bits
     for req in trace[:4]:
         alone, _ = serve.serve_pool([W.Request(arrival=0.0, spec=req.spec)], budget_bytes=1 << 30,
-                                    max_slots=1, keep_results=True, tune=tune)
+                                    max_slots=1, keep_results=True, tune=tune, two_sweep=two)
         mixed = recs[trace.index(req)]
         assert np.array_equal(alone[0]["u"], mixed["u"]) and alone[0]["residual"] == mixed["residual"]
 
 
-def test_pool_early_exit_matches_checked_oracle(env):
+@pytest.mark.parametrize("two", [False, True])
+def test_pool_early_exit_matches_checked_oracle(env, two):
     oracle, api, j3d, W = env
     n = (30, 26, 22)
     # tolerance reached after some check point
@@ -172,6 +176,7 @@ def test_pool_early_exit_matches_checked_oracle(env):
     want, want_r, done = oracle.jacobi(n, 500, seed=6, tol=tol, check_every=10)
     assert done < 500
     with api.Pool(1 << 30, max_slots=4) as pool:
+        pool.set_two_sweep(two)
         slot = pool.try_admit(j3d.Problem(n, seed=6), 500, tol=tol, check_every=10)
         finished = []
         while not finished:
@@ -216,6 +221,9 @@ def test_pool_tune_only_while_empty(env):
         slot = pool.try_admit(j3d.Problem((20, 12, 9), seed=1), 3)
         with pytest.raises(j3d.J3DError) as e:
             pool.set_tune(3, 32)
+        assert e.value.status == j3d.J3D_ESTATE
+        with pytest.raises(j3d.J3DError) as e:
+            pool.set_two_sweep(True)
         assert e.value.status == j3d.J3D_ESTATE
         while True:
             done, busy = pool.poll()
@@ -313,7 +321,8 @@ def test_batch_full_workload_matches_oracle(env):
 
 
 @pytest.mark.slow
-def test_pool_served_sizes_sample_matches_oracle(env):
+@pytest.mark.parametrize("two", [False, True])
+def test_pool_served_sizes_sample_matches_oracle(env, two):
     # a seeded sample of 32 requests of the served benchmark's mix (32..384
     # per axis, 50..2000 sweeps, residual every 50) plus its smallest and its
     # largest request, all admitted together, against the oracle's checked run
@@ -325,7 +334,7 @@ def test_pool_served_sizes_sample_matches_oracle(env):
     cells = [int(np.prod(r.spec.n)) for r in trace]
     pick += [int(np.argmin(cells)), int(np.argmax(cells))]
     reqs = [W.Request(arrival=0.0, spec=trace[i].spec) for i in pick]
-    recs, _ = serve.serve_pool(reqs, budget_bytes=40 << 30, max_slots=64, keep_results=True)
+    recs, _ = serve.serve_pool(reqs, budget_bytes=40 << 30, max_slots=64, keep_results=True, two_sweep=two)
     for rec, req in zip(recs, reqs):
         s = req.spec
         want, want_r, done = oracle.jacobi(s.n, s.iters, bc=s.bc, seed=s.seed, pid=s.pid, check_every=50,
