@@ -428,6 +428,8 @@ def main():
     ap.add_argument("--fill-cells", type=int, default=-1, help="serve workload: pool round policy (-1: default)")
     ap.add_argument("--pool-tune", default="", help="serve workload: variant,zchunk of the pool's rounds")
     ap.add_argument("--pool-two-sweep", action="store_true", help="serve workload: two sweeps per launch in the pool")
+    ap.add_argument("--serial-two-sweep", action="store_true",
+                    help="serve workload: the serial baseline solves with two sweeps per launch")
     ap.add_argument("--backlog-share", type=int, default=-1,
                     help="serve workload: rounds hold at least 1/k of the running cells (-1: default)")
     ap.add_argument("--odf-edge", type=int, default=256, help="odf workload: grid edge")

@@ -99,7 +99,7 @@ def serve_pool(trace, budget_bytes, max_slots=256, round_sweeps=50, check_every=
     return recs, rounds
 
 
-def serve_serial(trace, log=None, keep_results=False, tol=0.0, check_every=50):
+def serve_serial(trace, log=None, keep_results=False, tol=0.0, check_every=50, mode="graph"):
     """The same trace, one plain solve at a time in arrival order.  With tol > 0
     a solve runs in pieces of check_every sweeps (the last one shorter), reads
     the residual after each and stops at the first r <= tol, the same rule the
@@ -113,12 +113,12 @@ def serve_serial(trace, log=None, keep_results=False, tol=0.0, check_every=50):
             done = 0
             while True:
                 k = min(check_every, r.spec.iters - done)
-                res = s.run(k, mode="graph", residual=True)
+                res = s.run(k, mode=mode, residual=True)
                 done += k
                 if res <= tol or done >= r.spec.iters:
                     break
         else:
-            res = s.run(r.spec.iters, mode="graph", residual=True)
+            res = s.run(r.spec.iters, mode=mode, residual=True)
             done = r.spec.iters
         u = s.get_interior()
         s.close()
@@ -154,12 +154,13 @@ def bench_serve(args):
     count = int(getattr(args, "requests", 0) or 1100)
     warmup = min(100, count // 10)
     base = W.serve_trace(count=count, rate=1.0)
+    smode = "two_sweep" if getattr(args, "serial_two_sweep", False) else "graph"
     # serial capacity from a sample of the same request mix, after a few
     # untimed solves (first-call costs are not part of the service time)
-    serve_serial(W.rescale_arrivals(base[-5:], 1e9))
+    serve_serial(W.rescale_arrivals(base[-5:], 1e9), mode=smode)
     sample = base[: min(40, count)]
     t0 = time.perf_counter()
-    serve_serial(W.rescale_arrivals(sample, 1e9))
+    serve_serial(W.rescale_arrivals(sample, 1e9), mode=smode)
     mean_service = (time.perf_counter() - t0) / len(sample)
     load = float(getattr(args, "load", 0.8) or 0.8)
     rate = load / mean_service
@@ -176,7 +177,7 @@ def bench_serve(args):
     recs, rounds = serve_pool(trace, budget, log=_log, fill_cells=None if fill < 0 else fill, tune=ptune,
                               backlog_share=None if share < 0 else share, tol=tol, two_sweep=two)
     pool_sum = summarize(recs, warmup)
-    srecs = serve_serial(trace, log=_log, tol=tol)
+    srecs = serve_serial(trace, log=_log, tol=tol, mode=smode)
     serial_sum = summarize(srecs, warmup)
     # every request served in the mix against the same request solved alone:
     # the last sweep's residual (bit pattern) and the sweep count must agree
@@ -194,7 +195,7 @@ def bench_serve(args):
            "pool": pool_sum, "serial_plain": serial_sum, "rounds": rounds, "fill_cells": fill,
            "mix_vs_alone": {"requests": len(recs), "residual_bit_identical": same_res,
                             "sweeps_identical": same_it, "stopped_early": early},
-           "backlog_share": share, "pool_two_sweep": two,
+           "backlog_share": share, "pool_two_sweep": two, "serial_mode": smode,
            "pool_tune": list(ptune) if ptune else None,
            "config": {"workload": f"{count} Jacobi3D solve requests, Poisson arrivals at {rate:.2f}/s "
                                   f"({load} x serial capacity), per-axis size U{{32..384}}, 50..2000 sweeps, "
