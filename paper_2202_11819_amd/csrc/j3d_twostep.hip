@@ -28,15 +28,14 @@ namespace {
 constexpr double kW2 = 1.0 / 7.0;  // fl(1/7)
 constexpr int kXcds2 = 8;          // XCDs per MI355X
 
-constexpr int TX = 64;  // tile width: one 64-lane wave per row of w
 constexpr int NB = 3;   // planes of u held in registers per lane
 
 // Tile shapes: TX x TY cells of w, NT threads.  u^t covers the tile with a
 // two-cell ring, v the tile with a one-cell ring; each LDS plane ends in one
 // sink cell that takes the writes of lanes past the region.
-template <int TY_, int NT_>
+template <int TX_, int TY_, int NT_>
 struct Shape {
-    static constexpr int TY = TY_, NT = NT_;
+    static constexpr int TX = TX_, TY = TY_, NT = NT_;
     static constexpr int UX = TX + 4, UY = TY + 4, UP = UX * UY;
     static constexpr int VX = TX + 2, VY = TY + 2, VP = VX * VY;
     static constexpr int US = (UP + NT - 1) / NT;  // u cells per thread and plane
@@ -69,7 +68,7 @@ __device__ __forceinline__ int xcd_remap2(int i, int n)
 template <class S>
 __global__ __launch_bounds__(S::NT) void twostep_kernel(TwoStepArgs a)
 {
-    constexpr int TY = S::TY, NT = S::NT, UX = S::UX, UP = S::UP, VX = S::VX, VP = S::VP;
+    constexpr int TX = S::TX, TY = S::TY, NT = S::NT, UX = S::UX, UP = S::UP, VX = S::VX, VP = S::VP;
     constexpr int US = S::US, VS = S::VS, WS = S::WS, USLOT = S::USLOT, VSLOT = S::VSLOT;
     __shared__ double Us[4 * USLOT];
     __shared__ double Vs[4 * VSLOT];
@@ -295,13 +294,15 @@ __global__ __launch_bounds__(S::NT) void twostep_kernel(TwoStepArgs a)
     }
 }
 
-// 64 x 16 tiles of 512 threads: two workgroups share a compute unit.  A
-// 64 x 32 tile of 1024 threads, alone on its compute unit, measured 20% slower.
-using Tile16 = Shape<16, 512>;
+// 64 x 16 tiles of 512 threads: two workgroups share a compute unit.  Measured
+// alternatives: a 64 x 32 tile of 1024 threads, alone on its compute unit, 20%
+// slower; a 32 x 32 tile of 512 threads 5-7% slower on 512^3 and 1024^3 grids
+// (1% faster on the batched mix of small problems).
+using Tile16 = Shape<64, 16, 512>;
 
 int twostep_tiles(int ex, int ey, int ez, int zchunk, int *ntx, int *nty, int *ntz)
 {
-    *ntx = (ex + TX - 1) / TX;
+    *ntx = (ex + Tile16::TX - 1) / Tile16::TX;
     *nty = (ey + Tile16::TY - 1) / Tile16::TY;
     const int zc = zchunk > 0 && zchunk < ez ? zchunk : ez;
     *ntz = (ez + zc - 1) / zc;
