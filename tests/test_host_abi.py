@@ -168,6 +168,14 @@ def test_create_validates_before_device_work():
     assert e.value.status == j3d.J3D_EINVAL
 
 
+def test_two_sweep_entry_points_validate_handles():
+    # NULL handles are rejected before any device work
+    for fn, args in ((j3d._lib.j3d_batch_run_two_sweep, (None, None)), (j3d._lib.j3d_pool_set_two_sweep, (None, 1)),
+                     (j3d._lib.j3d_run, (None, 2, 9, None))):
+        assert fn(*args) == j3d.J3D_EINVAL
+    assert j3d.MODES["two_sweep"] == 9
+
+
 def _no_gpu_here():
     if os.path.exists("/dev/kfd"):
         return False
