@@ -25,6 +25,7 @@ namespace {
 // 64x32 tiles of 256 threads and 32-plane z-chunks: enough workgroups per
 // request that a round of a few mid-sized requests fills the GPU
 constexpr int kPoolZchunk = 32;
+constexpr int kPoolTwoZchunk = 64;  // z-chunk of the two-sweep rounds
 constexpr int64_t kPoolTilesPerReq = 4096;
 
 enum ReqState { R_FREE = 0, R_RUNNING, R_COPYING, R_DONE, R_REPORTED };
@@ -296,8 +297,8 @@ j3d_status j3d_pool_admit(j3d_pool *pl, const j3d_problem *p, int64_t max_iters,
     tiles_xy(vi, d.n[0], d.n[1], &ntx, &nty);
     const int64_t tiles = ntx * nty * ((d.n[2] + pl->zchunk - 1) / pl->zchunk);
     int tx2 = 0, ty2 = 0, tz2 = 0;
-    const int64_t tiles2 = pl->two_sweep ? twostep_tiles((int)d.n[0], (int)d.n[1], (int)d.n[2], kPoolZchunk, &tx2,
-                                                         &ty2, &tz2)
+    const int64_t tiles2 = pl->two_sweep ? twostep_tiles((int)d.n[0], (int)d.n[1], (int)d.n[2], kPoolTwoZchunk,
+                                                         &tx2, &ty2, &tz2)
                                          : 0;
     if (tiles > kPoolTilesPerReq || tiles2 > kPoolTilesPerReq)
         return set_error(J3D_EINVAL, "request of %lldx%lldx%lld needs %lld tiles, more than %lld",
@@ -450,7 +451,7 @@ j3d_status j3d_pool_step(j3d_pool *pl, int32_t sweeps)
             any_odd = any_odd || (k & 1) != 0;
             max_pairs = std::max<int64_t>(max_pairs, k / 2);
             const size_t at = tiles2.size();
-            twostep_make_tiles(&r.blk, 0, 1, kPoolZchunk, &tiles2);
+            twostep_make_tiles(&r.blk, 0, 1, kPoolTwoZchunk, &tiles2);
             for (size_t i = at; i < tiles2.size(); ++i) tiles2[i].block = s;
         }
         pl->round.push_back(RoundEntry{s, r.gen, base, limit, newbuf});
@@ -497,7 +498,7 @@ j3d_status j3d_pool_step(j3d_pool *pl, int32_t sweeps)
         a2.probs = reinterpret_cast<const ProbDesc *>(pl->arena + pl->lay.off_probs);
         a2.tiles = reinterpret_cast<const Tile *>(pl->arena + pl->lay.off_tiles);
         a2.res = res;
-        a2.zchunk = kPoolZchunk;
+        a2.zchunk = kPoolTwoZchunk;
         a2.tile_begin = 0;
         a2.tile_count = (int32_t)tiles2.size();
         for (int64_t s2 = 0; s2 < max_pairs && st == J3D_OK; ++s2) {
