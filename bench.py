@@ -422,6 +422,10 @@ def main():
     ap.add_argument("--requests", type=int, default=1100, help="serve workload: number of requests")
     ap.add_argument("--serve-dump", default="", help="serve workload: write per-request records here")
     ap.add_argument("--retune", action="store_true", help="batch workload: ignore the tuning cache")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="batch workload: time only the batched runs (with --tune: no autotuning in the process)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run the 2 GiB copy kernel once (counter calibration in profiled runs)")
     ap.add_argument("--load", type=float, default=0.8, help="serve workload: arrival rate / serial capacity")
     ap.add_argument("--tol", type=float, default=0.0,
                     help="serve workload: stop a request at the first residual check with r <= tol (0: never)")
@@ -450,6 +454,8 @@ def main():
     elif args.workload == "batch":
         from paper_2202_11819_amd import serve
         serve.bench_batch(args)
+        if args.copy_calib:
+            copy_bandwidth(reps=1)
     elif args.workload == "serve":
         from paper_2202_11819_amd import serve
         serve.bench_serve(args)

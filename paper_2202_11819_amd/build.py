@@ -35,18 +35,30 @@ def _run(cmd):
     subprocess.check_call(cmd)
 
 
-def build(verbose_resources: bool = False) -> str:
+def _stale(obj: str, src: str) -> bool:
+    """True unless obj is newer than its source and every header."""
+    if not os.path.exists(obj):
+        return True
+    deps = [src] + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
+    deps.append(os.path.join(ROOT, "include", "j3d.h"))
+    return any(os.path.getmtime(d) > os.path.getmtime(obj) for d in deps)
+
+
+def build(verbose_resources: bool = False, incremental: bool = False) -> str:
+    """Compile every source (incremental: only those older than their object) and link libj3d.so."""
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     for src in KERNEL_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
         extra = ["-Rpass-analysis=kernel-resource-usage"] if verbose_resources else []
-        _run([HIPCC, "-x", "hip", *COMMON, *DEVICE, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
+        if not incremental or _stale(obj, os.path.join(CSRC, src)):
+            _run([HIPCC, "-x", "hip", *COMMON, *DEVICE, *extra, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run([HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", *COMMON, "-c", os.path.join(CSRC, src),
-              "-o", obj])
+        if not incremental or _stale(obj, os.path.join(CSRC, src)):
+            _run([HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", *COMMON, "-c",
+                  os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp])
@@ -55,4 +67,4 @@ def build(verbose_resources: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose_resources="-v" in sys.argv)
+    build(verbose_resources="-v" in sys.argv, incremental="--incremental" in sys.argv)

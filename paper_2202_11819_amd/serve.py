@@ -212,7 +212,11 @@ def bench_batch(args):
     problems = [W.to_problem(s) for s in specs]
     iters = [s.iters for s in specs]
     lups = sum(p.cells * it for p, it in zip(problems, iters))
-    tune = tune_batch(problems, iters, log=_log, force=getattr(args, "retune", False))
+    fixed = getattr(args, "tune", "")
+    if fixed:
+        tune = tuple(int(v) for v in fixed.split(","))
+    else:
+        tune = tune_batch(problems, iters, log=_log, force=getattr(args, "retune", False))
     _log(f"[batch] tune {tune} ({j3d.variants()[tune[0]]})")
 
     def timed_batch(t, two_sweep=False):
@@ -228,6 +232,11 @@ def bench_batch(args):
 
     timed_batch(tune)
     tb = min(timed_batch(tune) for _ in range(2))
+    if getattr(args, "batch_only", False):
+        print(json.dumps({"metric": "batched FP64 Jacobi3D GLUP/s (256 problems, one launch per sweep)",
+                          "value": round(lups / tb / 1e9, 2), "unit": "GLUP/s", "batched_s": round(tb, 4),
+                          "tune": list(tune), "tile": list(j3d.variants()[tune[0]])}), flush=True)
+        return
     tdef = timed_batch(None)
     # the same batch with two sweeps per launch (all problems are undivided)
     timed_batch(tune, True)
