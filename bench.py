@@ -91,17 +91,21 @@ def copy_bandwidth(nbytes=2 << 30, reps=10):
 def cpu_baseline(n, target_seconds=15.0):
     """The oracle as it stands, on this host's cores, over a bounded sample.
 
-    The oracle's set-up (ghost fill, seeded interior) and copy-out are timed
-    separately by a 1-sweep run and subtracted, so the rate is per sweep."""
+    The timed copy is the oracle's source built -O3 -march=native on this
+    host (the parity build is portable; a CPU test checks that both give the
+    same bits).  The oracle's set-up (ghost fill, seeded interior) and
+    copy-out are timed separately by a 1-sweep run and subtracted, so the
+    rate is per sweep."""
     from oracle import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    threads = int(omp or 0) or len(os.sched_getaffinity(0))
     threads = max(1, min(threads, 64))
     cells = n[0] * n[1] * n[2]
 
     def rate(threads_, seconds):
         def timed(t):
             t0 = time.perf_counter()
-            oracle.jacobi(n, t, seed=1, nthreads=threads_)
+            oracle.jacobi(n, t, seed=1, nthreads=threads_, native=True)
             return time.perf_counter() - t0
 
         t1 = timed(1)
@@ -115,19 +119,37 @@ def cpu_baseline(n, target_seconds=15.0):
     return {"value": round(value, 4), "unit": "GLUP/s", "cores": threads, "kind": "oracle",
             "sample": f"{n[0]}x{n[1]}x{n[2]} seeded grid (the benchmark's problem), {k} sweeps taking "
                       f"{dt:.1f} s on {threads} threads, set-up and copy-out of a 1-sweep run subtracted",
+            "build": " ".join(["gcc"] + oracle.NATIVE_CFLAGS),
             "one_thread_value": round(one, 4), "one_thread_sample": f"{k1} sweeps taking {dt1:.1f} s",
-            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+            "cpu_model": cpu_model(), "omp_num_threads": omp or None, "host_cpus": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0))}
 
 
 def cpu_model():
+    """lscpu's model name (with vendor and family when the name is generic)."""
+    import subprocess
+    fields = {}
     try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
-    except OSError:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
         pass
-    return "unknown"
+    name = fields.get("Model name", "")
+    if not name:
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        name = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    extra = [f"{k} {fields[k]}" for k in ("Vendor ID", "CPU family", "Model", "Stepping", "Socket(s)",
+                                          "Core(s) per socket", "Thread(s) per core") if k in fields]
+    return f"{name or 'unknown'} ({', '.join(extra)})" if extra else (name or "unknown")
 
 
 def bench_overdecomposed(args):

@@ -158,10 +158,12 @@ typedef struct j3d_pool j3d_pool;
 
 /* ---- host-only queries (no device needed) ------------------------------ */
 
-/* Thread-local text of the last non-OK status on this thread ("" if none). */
+/* Thread-local text of the last non-OK status on this thread ("" if none).
+ * Not in the paper: error reporting of this library.                         */
 const char *j3d_last_error(void);
 
-/* Library version string. */
+/* Library version string (names the device architecture it was built for).
+ * Not in the paper.                                                          */
 const char *j3d_version(void);
 
 /* Surface-minimising split of an n[0] x n[1] x n[2] grid into exactly `parts`
@@ -173,75 +175,110 @@ const char *j3d_version(void);
  * parts > 2^22 (the block limit of a problem) or no factorisation fits.      */
 j3d_status j3d_auto_split(const int64_t n[3], int32_t parts, int32_t nblk_out[3]);
 
-/* Resolved decomposition of a problem: nblk_out[3] blocks per axis and, if
+/* Resolved decomposition of a problem (Sec. II-A, Fig. 1: the global grid is
+ * cut into blocks, one per process or chare; Sec. IV-A: over-decomposition
+ * into more blocks than GPUs): nblk_out[3] blocks per axis and, if
  * extents_out is non-NULL, the extents along x, then y, then z
- * (nblk[0]+nblk[1]+nblk[2] values, at most cap).  Auto splits whose counts
- * do not divide n[a] give the first n[a] % nblk[a] blocks one extra cell.   */
+ * (nblk[0]+nblk[1]+nblk[2] values, at most cap; EINVAL if more).  Auto
+ * splits whose counts do not divide n[a] give the first n[a] % nblk[a]
+ * blocks one extra cell.  Host only.                                         */
 j3d_status j3d_block_extents(const j3d_problem *p, int32_t nblk_out[3],
                              int64_t *extents_out, int64_t cap);
 
-/* Device bytes j3d_create needs for this problem (fields, halo storage,
- * send/receive buffers of the unfused modes, descriptor tables, staging).   */
+/* Device bytes j3d_create needs for this problem: the two iterates of every
+ * block (Sec. III-C: previous and current iterate in two buffers), their halo
+ * storage, the send/receive halo buffers of the unfused modes (Fig. 1),
+ * descriptor tables and staging.  Host only; EINVAL for a bad problem.       */
 j3d_status j3d_arena_bytes(const j3d_problem *p, uint64_t *bytes);
 
-/* Bytes of the two field copies only (interior plus halo storage). */
+/* Bytes of the two field copies only (interior plus halo storage): the
+ * per-GPU memory the paper quotes for its weak-scaling grids (Sec. IV-B).
+ * Host only.                                                                 */
 j3d_status j3d_field_bytes(const j3d_problem *p, uint64_t *bytes);
 
 /* Compiled sweep tile shapes: variant i covers tile_x x tile_y cells of an
  * x-y plane with `threads` threads.  tile_x == 0 marks a flattened variant:
  * its tiles are whole row segments sized per block (any width, up to tile_y
  * cells, every thread owning tile_y / threads cells).  Returns EINVAL past
- * the last variant.                                                          */
+ * the last variant.  Not in the paper: kernel shapes of this implementation. */
 j3d_status j3d_variant_info(int32_t variant, int32_t *tile_x, int32_t *tile_y,
                             int32_t *threads);
 
 /* ---- plain solver -------------------------------------------------------- */
 
 /* Lay out problem p in dev_arena (arena_bytes >= j3d_arena_bytes(p)) and
- * enqueue the seeded initialisation on hip_stream.  ENOMEM if the arena is too
- * small, EDEVICE if no gfx950 device is current.                             */
+ * enqueue the seeded initialisation on hip_stream.  The problem is the
+ * paper's (Sec. II-A, Fig. 1): a global 3-D grid cut into blocks, each with
+ * six halo faces, updated for a fixed number of iterations; the seeded
+ * interior and the Dirichlet values are readings (the paper states neither).
+ * EINVAL for a bad problem or NULL/unaligned arena, ENOMEM if the arena is
+ * too small, EDEVICE if no gfx950 device is current; all before device work.
+ * The solver keeps pointers into the arena, which must outlive it.           */
 j3d_status j3d_create(const j3d_problem *p, void *dev_arena, uint64_t arena_bytes,
                       void *hip_stream, j3d_solver **out);
 
-/* Replace the current interior with src (dense nx*ny*nz).  src_on_device: 1 if
- * src is device memory, 0 for host memory (then the call synchronises).     */
+/* Replace the current interior with src (dense nx*ny*nz) and reset the
+ * iteration count to 0.  src_on_device: 1 if src is device memory, 0 for host
+ * memory (then the call synchronises).  Not in the paper (which initialises
+ * in place): loads any initial iterate, and with j3d_get_interior lets a
+ * solve be checkpointed and resumed.                                        */
 j3d_status j3d_set_interior(j3d_solver *s, const double *src, int src_on_device);
 
 /* Per-cell Dirichlet values for global face f (0..5), overriding bc[f].
  * Layouts: x-faces ny*nz (y fastest), y-faces nx*nz (x fastest), z-faces nx*ny
- * (x fastest).  src_on_device as above.                                     */
+ * (x fastest).  src_on_device as above.  EINVAL for f outside 0..5 or a NULL
+ * src.  Not in the paper (it states no boundary condition): a per-cell
+ * boundary lets linear fields be checked as exact fixed points.             */
 j3d_status j3d_set_face(j3d_solver *s, int32_t face, const double *src, int src_on_device);
 
-/* Choose the sweep kernel shape (see j3d_tune); NULL restores the default. */
+/* Choose the sweep kernel shape (see j3d_tune); NULL restores the default.
+ * EINVAL for a variant out of range or a negative field.  Not in the paper. */
 j3d_status j3d_set_tune(j3d_solver *s, const j3d_tune *t);
 
-/* The shape in use (the default chosen by block size until j3d_set_tune). */
+/* The shape in use (the default chosen by block size until j3d_set_tune).
+ * Not in the paper.                                                          */
 j3d_status j3d_get_tune(const j3d_solver *s, j3d_tune *out);
 
-/* Enqueue `iters` (>= 0) Jacobi iterations in the given mode.  If residual_out
- * is non-NULL the last sweep's residual is written there and the call
- * synchronises; otherwise it returns once the work is enqueued.              */
+/* Enqueue `iters` (>= 0) Jacobi iterations in the given mode: the paper's
+ * iteration loop (Fig. 1; Fig. 3 for its GPU form: pack, exchange in six
+ * directions, unpack, update, with the buffers swapped every iteration,
+ * Sec. III-C), executed as the chosen j3d_mode (fusion Sec. III-D-1, graphs
+ * Sec. III-D-2, host staging Sec. II-B, overlap Fig. 1).  If residual_out is
+ * non-NULL the last sweep's residual is written there and the call
+ * synchronises (the residual is a reading: the paper runs a fixed count);
+ * otherwise it returns once the work is enqueued.  EINVAL for iters < 0 or
+ * an unknown mode, before any device work.                                   */
 j3d_status j3d_run(j3d_solver *s, int64_t iters, j3d_mode mode, double *residual_out);
 
-/* Iterations performed since creation or the last j3d_set_interior. */
+/* Iterations performed since creation or the last j3d_set_interior.  Not in
+ * the paper (resume bookkeeping).                                            */
 j3d_status j3d_iters_done(const j3d_solver *s, int64_t *iters);
 
-/* Copy the current interior to dst (dense nx*ny*nz).  Synchronises for host
- * destinations; device destinations are written asynchronously.            */
+/* Copy the current interior to dst (dense nx*ny*nz, independent of the
+ * decomposition).  Synchronises for host destinations; device destinations
+ * are written asynchronously.  Not in the paper (readback of the result).   */
 j3d_status j3d_get_interior(j3d_solver *s, double *dst, int dst_on_device);
 
 /* Release the solver's host objects (graphs, tables); the arena stays the
- * caller's.  Synchronises the stream first.                                 */
+ * caller's.  Synchronises the stream first.  Not in the paper.              */
 j3d_status j3d_destroy(j3d_solver *s);
 
-/* ---- batched form: many independent problems, one launch per step ------- */
+/* ---- batched form: many independent problems, one launch per step -------
+ * Not in the paper.  Each problem is the paper's Jacobi3D problem (Sec. II-A);
+ * the form extends fusion strategy C (one kernel per iteration, Sec. III-D-1)
+ * across independent problems.                                              */
 
-/* Device bytes for a batch of `count` problems. */
+/* Device bytes for a batch of `count` problems (host only). */
 j3d_status j3d_batch_arena_bytes(int32_t count, const j3d_problem *probs, uint64_t *bytes);
 
 /* Lay out `count` problems (each with its own decomposition, boundary and
  * seed) and their iteration counts iters[i] >= 0, and enqueue their seeded
- * initialisation.  tune may be NULL (default shape).                        */
+ * initialisation.  tune: the kernel shape for every launch of the batch, as
+ * resolved by the caller's autotuner from its tune cache (the cache itself,
+ * a file of measured shapes per device and problem mix, is kept by the
+ * caller, not parsed here); NULL picks the default shape.  EINVAL for count
+ * < 1, NULL arrays, a bad problem or a bad shape; ENOMEM if the arena is too
+ * small; all before device work.                                            */
 j3d_status j3d_batch_create(int32_t count, const j3d_problem *probs, const int64_t *iters,
                             void *dev_arena, uint64_t arena_bytes, void *hip_stream,
                             const j3d_tune *tune, j3d_batch **out);
@@ -268,14 +305,22 @@ j3d_status j3d_batch_get_interior(j3d_batch *b, int32_t i, double *dst, int dst_
 
 j3d_status j3d_batch_destroy(j3d_batch *b);
 
-/* ---- served form: continuous batching under an HBM budget ---------------- */
+/* ---- served form: continuous batching under an HBM budget ----------------
+ * Not in the paper.  Each request is the paper's Jacobi3D problem
+ * (Sec. II-A) as one block; rounds use the fused update (Sec. III-D-1), and
+ * finished work is found by polling events, as the paper detects the
+ * completion of asynchronous GPU work (Sec. III-A).                         */
 
-/* Device bytes one request of problem p occupies in a pool. */
+/* Device bytes one request of problem p occupies in a pool (host only;
+ * EINVAL unless p is a single-block problem).                               */
 j3d_status j3d_pool_request_bytes(const j3d_problem *p, uint64_t *bytes);
 
 /* A pool over dev_arena: budget_bytes of it hold request grids, the rest (see
- * j3d_pool_overhead_bytes) its tables.  At most max_slots requests are
- * resident.  The pool creates one extra stream for result copies.           */
+ * j3d_pool_overhead_bytes) its tables; arena_bytes (>= overhead + budget) is
+ * the arena's size, checked so that a short arena is refused (ENOMEM) rather
+ * than overrun.  At most max_slots (1..65536) requests are resident.  The
+ * pool creates one extra stream for result copies.  EINVAL for NULL or
+ * unaligned arena, budget 0 or max_slots out of range; before device work.  */
 j3d_status j3d_pool_overhead_bytes(int32_t max_slots, uint64_t *bytes);
 j3d_status j3d_pool_create(void *dev_arena, uint64_t arena_bytes, uint64_t budget_bytes,
                            int32_t max_slots, void *hip_stream, j3d_pool **out);
@@ -283,9 +328,13 @@ j3d_status j3d_pool_create(void *dev_arena, uint64_t arena_bytes, uint64_t budge
 /* Admit a request: solve p for at most max_iters sweeps, evaluating the
  * residual every check_every sweeps (0: only at the end) and at max_iters,
  * stopping once it is <= tol (tol <= 0: never early).  host_result (nx*ny*nz
- * doubles, best page-locked) receives the final interior when the request
- * finishes.  EBUSY without a free slot, EBUDGET without enough free budget;
- * nothing changes then.  The request joins the next round.                 */
+ * doubles, best page-locked, or NULL) receives the final interior by an
+ * asynchronous copy as soon as the request finishes, while later rounds run;
+ * with NULL the result stays in device memory until j3d_pool_fetch.  The
+ * caller keeps host_result valid until the slot is reported done or is
+ * released.  EBUSY without a free slot, EBUDGET without enough free budget,
+ * EINVAL for a bad problem, max_iters < 0 or check_every < 0; nothing
+ * changes then.  The request joins the next round.                         */
 j3d_status j3d_pool_admit(j3d_pool *pl, const j3d_problem *p, int64_t max_iters, double tol,
                           int32_t check_every, double *host_result, int32_t *slot);
 
@@ -329,13 +378,23 @@ j3d_status j3d_pool_set_two_sweep(j3d_pool *pl, int32_t enable);
 j3d_status j3d_pool_poll(j3d_pool *pl, int32_t *done, int32_t cap, int32_t *n_done,
                          int32_t *round_busy);
 
-/* Residual and sweep count of a finished request. */
+/* Residual and sweep count of a finished request (either may be NULL).
+ * ESTATE until the request is reported done by j3d_pool_poll.                */
 j3d_status j3d_pool_result(j3d_pool *pl, int32_t slot, double *residual, int64_t *iters_done);
 
-/* Free a finished (or still queued/running: cancel) request's slot and bytes. */
+/* Fetch a finished request: its final interior (dense nx*ny*nz, x fastest)
+ * is copied to host_dst (NULL: not copied) and its residual and sweep count
+ * are written (each may be NULL).  Synchronises with the copy.  Works
+ * whether or not a host_result was given at admission (the result stays in
+ * device memory until release).  EINVAL for a NULL pool or a slot out of
+ * range, ESTATE for a slot that is free or not finished; before any copy.   */
+j3d_status j3d_pool_fetch(j3d_pool *pl, int32_t slot, double *host_dst, double *residual, int64_t *iters_done);
+
+/* Free a finished (or still queued/running: cancel) request's slot and bytes.
+ * Waits for a result copy still in flight.  ESTATE for a free slot.          */
 j3d_status j3d_pool_release(j3d_pool *pl, int32_t slot);
 
-/* Occupancy: resident requests and bytes in use. */
+/* Occupancy: resident requests and bytes in use (host only). */
 j3d_status j3d_pool_usage(const j3d_pool *pl, int32_t *slots_used, uint64_t *bytes_used);
 
 j3d_status j3d_pool_destroy(j3d_pool *pl);
@@ -343,10 +402,12 @@ j3d_status j3d_pool_destroy(j3d_pool *pl);
 /* ---- measurement helpers ------------------------------------------------- */
 
 /* Enqueue a plain device copy of `bytes` (multiple of 16) from src to dst: the
- * streaming-bandwidth reference kernel used to calibrate HBM counters.      */
+ * streaming-bandwidth reference kernel used to calibrate HBM counters.  Not
+ * in the paper (measurement).                                               */
 j3d_status j3d_device_copy(void *dst, const void *src, uint64_t bytes, void *hip_stream);
 
-/* Number of compute units of the current device (EDEVICE without a device). */
+/* Number of compute units of the current device (EDEVICE without a device).
+ * Not in the paper.                                                          */
 j3d_status j3d_device_cus(int32_t *cus);
 
 #ifdef __cplusplus

@@ -17,13 +17,19 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "j3d_oracle.c")
 LIB = os.path.join(HERE, "liboracle_j3d.so")
 
-# IEEE binary64, no contraction, no fast-math (denormals stay on).
-CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+# IEEE binary64, no contraction, no fast-math (denormals stay on).  One flag
+# list serves both builds below; neither option changes a result bit
+# (tests/test_oracle_pins.py compares the two builds).
+CFLAGS = ["-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
           "-fno-fast-math", "-Wall", "-Wextra"]
+# The timing copy is also tuned for the host it runs on.  It is compiled on
+# that host, into a private directory, and never shipped: code built for one
+# machine's vector extensions may not run on another's.
+NATIVE_CFLAGS = CFLAGS + ["-march=native"]
 
 
 def compile_oracle(force: bool = False) -> str:
-    """Compile the oracle with gcc; returns the library path."""
+    """Compile the parity build (portable code) with gcc; returns the library path."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", *CFLAGS, SRC, "-o", tmp, "-lm"])
@@ -31,30 +37,46 @@ def compile_oracle(force: bool = False) -> str:
     return LIB
 
 
-_lib = None
+_native_path = None
 
 
-def lib() -> ctypes.CDLL:
-    global _lib
-    if _lib is None:
-        _lib = ctypes.CDLL(compile_oracle())
+def compile_native() -> str:
+    """Compile the timing copy (-march=native) for this host, once per process."""
+    global _native_path
+    if _native_path is None:
+        import tempfile
+        d = tempfile.mkdtemp(prefix="j3d_oracle_native_")
+        path = os.path.join(d, "liboracle_j3d_native.so")
+        subprocess.check_call(["gcc", *NATIVE_CFLAGS, SRC, "-o", path, "-lm"])
+        _native_path = path
+    return _native_path
+
+
+_libs = {}
+
+
+def lib(native: bool = False) -> ctypes.CDLL:
+    """The parity build, or (native=True) the host-tuned timing copy."""
+    if native not in _libs:
+        L = ctypes.CDLL(compile_native() if native else compile_oracle())
         i64, u64, dp = ctypes.c_int64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)
-        _lib.oracle_splitmix64_seq.argtypes = [u64, i64, ctypes.POINTER(u64)]
-        _lib.oracle_splitmix64_seq.restype = None
-        _lib.oracle_init_interior.argtypes = [i64, i64, i64, u64, u64, dp]
-        _lib.oracle_init_interior.restype = None
-        _lib.oracle_init_cell.argtypes = [i64, i64, u64, u64, i64, i64, i64]
-        _lib.oracle_init_cell.restype = ctypes.c_double
-        _lib.oracle_jacobi.argtypes = [i64, i64, i64, dp, u64, u64, dp,
-                                       ctypes.POINTER(dp), i64, ctypes.c_double, i64,
-                                       dp, dp, ctypes.POINTER(i64), ctypes.c_int]
-        _lib.oracle_jacobi.restype = ctypes.c_int
-        _lib.oracle_cell_after.argtypes = [i64, i64, i64, u64, u64, dp, i64, i64, i64,
-                                           i64, dp]
-        _lib.oracle_cell_after.restype = ctypes.c_int
-        _lib.oracle_max_threads.argtypes = []
-        _lib.oracle_max_threads.restype = ctypes.c_int
-    return _lib
+        L.oracle_splitmix64_seq.argtypes = [u64, i64, ctypes.POINTER(u64)]
+        L.oracle_splitmix64_seq.restype = None
+        L.oracle_init_interior.argtypes = [i64, i64, i64, u64, u64, dp]
+        L.oracle_init_interior.restype = None
+        L.oracle_init_cell.argtypes = [i64, i64, u64, u64, i64, i64, i64]
+        L.oracle_init_cell.restype = ctypes.c_double
+        L.oracle_jacobi.argtypes = [i64, i64, i64, dp, u64, u64, dp,
+                                    ctypes.POINTER(dp), i64, ctypes.c_double, i64,
+                                    dp, dp, ctypes.POINTER(i64), ctypes.c_int]
+        L.oracle_jacobi.restype = ctypes.c_int
+        L.oracle_cell_after.argtypes = [i64, i64, i64, u64, u64, dp, i64, i64, i64,
+                                        i64, dp]
+        L.oracle_cell_after.restype = ctypes.c_int
+        L.oracle_max_threads.argtypes = []
+        L.oracle_max_threads.restype = ctypes.c_int
+        _libs[native] = L
+    return _libs[native]
 
 
 def _dp(a: np.ndarray):
@@ -80,8 +102,9 @@ def init_cell(n, seed: int, pid: int, i: int, j: int, k: int) -> float:
 
 
 def jacobi(n, t_max: int, bc=(0.0,) * 6, u0=None, seed: int = 1, pid: int = 0,
-           faces=None, tol: float = 0.0, check_every: int = 0, nthreads: int = 1):
-    """Run the oracle; returns (u (nz,ny,nx), residual, iters_done)."""
+           faces=None, tol: float = 0.0, check_every: int = 0, nthreads: int = 1, native: bool = False):
+    """Run the oracle; returns (u (nz,ny,nx), residual, iters_done).
+    native=True runs the host-tuned timing copy (same bits)."""
     nx, ny, nz = (int(v) for v in n)
     out = np.empty((nz, ny, nx), dtype=np.float64)
     bca = np.ascontiguousarray(np.asarray(bc, dtype=np.float64))
@@ -105,7 +128,7 @@ def jacobi(n, t_max: int, bc=(0.0,) * 6, u0=None, seed: int = 1, pid: int = 0,
         face_ptrs = arr
     res = ctypes.c_double(0.0)
     done = ctypes.c_int64(0)
-    rc = lib().oracle_jacobi(nx, ny, nz, u0p, seed, pid, _dp(bca), face_ptrs, int(t_max),
+    rc = lib(native).oracle_jacobi(nx, ny, nz, u0p, seed, pid, _dp(bca), face_ptrs, int(t_max),
                              float(tol), int(check_every), _dp(out), ctypes.byref(res),
                              ctypes.byref(done), int(nthreads))
     if rc != 0:

@@ -5,6 +5,8 @@ stream and marshal arrays; every computation runs in libj3d.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 import torch
 
@@ -117,26 +119,58 @@ class Batch:
 
 
 class Pool:
-    """Continuous batching of solve requests under an HBM budget."""
+    """Continuous batching of solve requests under an HBM budget.
+
+    Finished results are copied asynchronously into page-locked host buffers
+    (one per admitted request).  Those buffers are recycled: a released
+    request's buffer goes back to a free list of size classes (1/8 octave
+    apart), and a buffer is allocated only when no free one fits, and only
+    after a cheap check that the pool has a free slot and budget, so a request
+    that cannot be admitted yet costs no allocation."""
 
     def __init__(self, budget_bytes, max_slots=256, stream=None, device="cuda"):
         self.overhead = C.j3d_pool_overhead_bytes(max_slots)
-        self.arena_bytes = self.overhead + int(budget_bytes)
+        self.budget = int(budget_bytes)
+        self.arena_bytes = self.overhead + self.budget
         self.arena = torch.empty(self.arena_bytes, dtype=torch.uint8, device=device)
         self.stream = _stream(stream)
         self.max_slots = max_slots
-        self.h = C.j3d_pool_create(self.arena.data_ptr(), self.arena_bytes, int(budget_bytes), max_slots,
+        self.h = C.j3d_pool_create(self.arena.data_ptr(), self.arena_bytes, self.budget, max_slots,
                                    self.stream.cuda_stream)
-        self.results = {}
+        self.results = {}       # slot -> (pinned host buffer or None, (nz, ny, nx))
+        self._free_host = []    # released pinned buffers, reused by later requests
 
-    def try_admit(self, problem, max_iters, tol=0.0, check_every=50):
-        """Returns the slot or None when no slot / budget is free."""
+    @staticmethod
+    def _size_class(cells):
+        return max(1, int(2.0 ** (math.ceil(8 * math.log2(max(cells, 1))) / 8)))
+
+    def _host_buffer(self, cells):
+        best = None
+        for i, buf in enumerate(self._free_host):
+            if buf.numel() >= cells and (best is None or buf.numel() < self._free_host[best].numel()):
+                best = i
+        if best is not None and self._free_host[best].numel() <= 2 * cells:
+            return self._free_host.pop(best)
+        return torch.empty(max(cells, self._size_class(cells)), dtype=torch.float64, pin_memory=True)
+
+    def try_admit(self, problem, max_iters, tol=0.0, check_every=50, host=True):
+        """Returns the slot or None when no slot / budget is free.  host=False:
+        the result stays on the device until fetch()."""
         n = problem.n
-        host = torch.empty(n[0] * n[1] * n[2], dtype=torch.float64, pin_memory=True)
-        st, slot = C.j3d_pool_try_admit(self.h, problem, max_iters, tol, check_every, host.data_ptr())
+        cells = n[0] * n[1] * n[2]
+        buf = None
+        if host:
+            used, nbytes = C.j3d_pool_usage(self.h)
+            if used >= self.max_slots or nbytes + C.j3d_pool_request_bytes(problem) > self.budget:
+                return None
+            buf = self._host_buffer(cells)
+        st, slot = C.j3d_pool_try_admit(self.h, problem, max_iters, tol, check_every,
+                                        buf.data_ptr() if buf is not None else None)
         if st != C.J3D_OK:
+            if buf is not None:
+                self._free_host.append(buf)  # fragmented budget: keep the buffer for the retry
             return None
-        self.results[slot] = (host, (n[2], n[1], n[0]))
+        self.results[slot] = (buf, (n[2], n[1], n[0]))
         return slot
 
     def step(self, sweeps=50):
@@ -157,14 +191,28 @@ class Pool:
         return C.j3d_pool_poll(self.h, self.max_slots)
 
     def result(self, slot):
-        """(interior as numpy (nz,ny,nx), residual, sweeps done) of a finished slot."""
+        """(interior as numpy (nz,ny,nx), residual, sweeps done) of a finished slot.
+        The array views the slot's host buffer: copy it to keep it past release."""
+        buf, shape = self.results[slot]
+        if buf is None:
+            return self.fetch(slot)
         r, it = C.j3d_pool_result(self.h, slot)
-        host, shape = self.results[slot]
-        return host.numpy().reshape(shape), r, it
+        return buf.numpy()[: shape[0] * shape[1] * shape[2]].reshape(shape), r, it
+
+    def fetch(self, slot):
+        """(interior, residual, sweeps done) copied from the device by j3d_pool_fetch (synchronous)."""
+        _, shape = self.results[slot]
+        out = np.empty(shape, dtype=np.float64)
+        r, it = C.j3d_pool_fetch(self.h, slot, out.ctypes.data)
+        return out, r, it
 
     def release(self, slot):
         C.j3d_pool_release(self.h, slot)
-        self.results.pop(slot, None)
+        buf, _ = self.results.pop(slot, (None, None))
+        if buf is not None:
+            self._free_host.append(buf)
+            if len(self._free_host) > 64:  # bound the idle page-locked memory
+                self._free_host.pop(0)
 
     def usage(self):
         return C.j3d_pool_usage(self.h)

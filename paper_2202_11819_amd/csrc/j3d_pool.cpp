@@ -195,10 +195,14 @@ j3d_status start_copy(j3d_pool *pl, int32_t slot)
     if (st != J3D_OK) return st;
     st = hip_status(hipStreamWaitEvent(pl->copy_stream, r.gather_ev, 0), "copy wait");
     if (st != J3D_OK) return st;
-    const size_t bytes = (size_t)(r.n[0] * r.n[1] * r.n[2]) * sizeof(double);
-    st = hip_status(hipMemcpyAsync(r.host_result, dst, bytes, hipMemcpyDeviceToHost, pl->copy_stream),
-                    "result copy");
-    if (st != J3D_OK) return st;
+    // without a host buffer the gathered interior waits in the free buffer
+    // until j3d_pool_fetch or release
+    if (r.host_result) {
+        const size_t bytes = (size_t)(r.n[0] * r.n[1] * r.n[2]) * sizeof(double);
+        st = hip_status(hipMemcpyAsync(r.host_result, dst, bytes, hipMemcpyDeviceToHost, pl->copy_stream),
+                        "result copy");
+        if (st != J3D_OK) return st;
+    }
     st = hip_status(hipEventRecord(r.copy_ev, pl->copy_stream), "copy event");
     if (st != J3D_OK) return st;
     r.state = R_COPYING;
@@ -285,7 +289,7 @@ j3d_status j3d_pool_create(void *dev_arena, uint64_t arena_bytes, uint64_t budge
 j3d_status j3d_pool_admit(j3d_pool *pl, const j3d_problem *p, int64_t max_iters, double tol,
                           int32_t check_every, double *host_result, int32_t *slot)
 {
-    if (!pl || !p || !host_result || !slot) return set_error(J3D_EINVAL, "NULL argument");
+    if (!pl || !p || !slot) return set_error(J3D_EINVAL, "NULL argument");
     if (max_iters < 0) return set_error(J3D_EINVAL, "max_iters %lld < 0", (long long)max_iters);
     if (check_every < 0) return set_error(J3D_EINVAL, "check_every %d < 0", check_every);
     Decomp d;
@@ -575,6 +579,27 @@ j3d_status j3d_pool_result(j3d_pool *pl, int32_t slot, double *residual, int64_t
     if (slot < 0 || slot >= pl->max_slots) return set_error(J3D_EINVAL, "slot %d out of range", slot);
     const Req &r = pl->reqs[slot];
     if (r.state != R_DONE && r.state != R_REPORTED) return set_error(J3D_ESTATE, "slot %d has no result", slot);
+    if (residual) *residual = r.residual;
+    if (iters_done) *iters_done = r.iters_done;
+    return J3D_OK;
+}
+
+j3d_status j3d_pool_fetch(j3d_pool *pl, int32_t slot, double *host_dst, double *residual, int64_t *iters_done)
+{
+    if (!pl) return set_error(J3D_EINVAL, "pool is NULL");
+    if (slot < 0 || slot >= pl->max_slots) return set_error(J3D_EINVAL, "slot %d out of range", slot);
+    const Req &r = pl->reqs[slot];
+    if (r.state != R_DONE && r.state != R_REPORTED) return set_error(J3D_ESTATE, "slot %d has no result", slot);
+    if (host_dst) {
+        // the finished iterate was gathered (dense, x fastest) into the
+        // request's other field buffer, which no round touches until release
+        const double *src = reinterpret_cast<const double *>(pl->arena) + r.blk.off[r.buf ^ 1];
+        const size_t bytes = (size_t)(r.n[0] * r.n[1] * r.n[2]) * sizeof(double);
+        j3d_status st = hip_status(hipMemcpyAsync(host_dst, src, bytes, hipMemcpyDeviceToHost, pl->copy_stream),
+                                   "fetch copy");
+        if (st == J3D_OK) st = hip_status(hipStreamSynchronize(pl->copy_stream), "fetch wait");
+        if (st != J3D_OK) return st;
+    }
     if (residual) *residual = r.residual;
     if (iters_done) *iters_done = r.iters_done;
     return J3D_OK;

@@ -118,6 +118,7 @@ _SIGS = {
     "j3d_pool_set_two_sweep": ([_H, c_int32], c_int),
     "j3d_pool_poll": ([_H, POINTER(c_int32), c_int32, POINTER(c_int32), POINTER(c_int32)], c_int),
     "j3d_pool_result": ([_H, c_int32, _DP, POINTER(c_int64)], c_int),
+    "j3d_pool_fetch": ([_H, c_int32, c_void_p, _DP, POINTER(c_int64)], c_int),
     "j3d_pool_release": ([_H, c_int32], c_int),
     "j3d_pool_usage": ([_H, POINTER(c_int32), POINTER(c_uint64)], c_int),
     "j3d_pool_destroy": ([_H], c_int),
@@ -405,6 +406,15 @@ def j3d_pool_result(h, slot: int):
     r = c_double()
     it = c_int64()
     _check(_lib.j3d_pool_result(h, int(slot), byref(r), byref(it)), "j3d_pool_result")
+    return r.value, it.value
+
+
+def j3d_pool_fetch(h, slot: int, host_dst_ptr=None):
+    """(residual, sweeps done) of a finished slot; its interior is copied to
+    host_dst_ptr (nx*ny*nz doubles) when given.  Synchronises."""
+    r, it = c_double(0.0), c_int64(0)
+    _check(_lib.j3d_pool_fetch(h, int(slot), c_void_p(host_dst_ptr) if host_dst_ptr else None, byref(r),
+                               byref(it)), "j3d_pool_fetch")
     return r.value, it.value
 
 

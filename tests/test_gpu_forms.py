@@ -275,6 +275,52 @@ def test_pool_admission_limits_and_errors(env):
         assert st == j3d.J3D_EBUSY
 
 
+def test_pool_fetch_through_the_c_abi_matches_oracle(env):
+    # j3d_pool_fetch copies a finished request's interior from the device,
+    # whether the request was admitted without a host buffer (result kept on
+    # the device) or with one (copied asynchronously at the finish)
+    import ctypes
+    oracle, api, j3d, W = env
+    L = j3d._lib
+    specs = [((37, 21, 13), 41, 0.0, 10), ((16, 40, 9), 23, 0.0, 0), ((30, 26, 22), 500, None, 10)]
+    _, tol, _ = oracle.jacobi(specs[2][0], 60, seed=4, pid=2)
+    with api.Pool(1 << 29, max_slots=4) as pool:
+        slots, hosts = [], []
+        for i, (n, it, t, ce) in enumerate(specs):
+            p = j3d.Problem(n, seed=4, pid=i, bc=(0.25, -0.5, 1.0, 0.0, -1.0, 0.5))
+            host = np.zeros(n[0] * n[1] * n[2]) if i == 1 else None
+            hosts.append(host)
+            s = ctypes.c_int32(-1)
+            st = L.j3d_pool_admit(pool.h, ctypes.byref(p.c), it, tol if t is None else t, ce,
+                                  host.ctypes.data if host is not None else None, ctypes.byref(s))
+            assert st == j3d.J3D_OK
+            slots.append(s.value)
+        # not finished yet: ESTATE, nothing written
+        r, k = ctypes.c_double(-1.0), ctypes.c_int64(-1)
+        assert L.j3d_pool_fetch(pool.h, slots[0], None, ctypes.byref(r), ctypes.byref(k)) == j3d.J3D_ESTATE
+        assert r.value == -1.0 and k.value == -1
+        assert L.j3d_pool_fetch(pool.h, 4, None, None, None) == j3d.J3D_EINVAL
+        done = set()
+        while len(done) < len(slots):
+            got, busy = pool.poll()
+            done.update(got)
+            if not busy and len(done) < len(slots):
+                pool.step(50)
+        for i, (n, it, t, ce) in enumerate(specs):
+            want, want_r, want_k = oracle.jacobi(n, it, bc=(0.25, -0.5, 1.0, 0.0, -1.0, 0.5), seed=4, pid=i,
+                                                 tol=tol if t is None else t, check_every=ce, nthreads=NTH)
+            out = np.full((n[2], n[1], n[0]), np.nan)
+            assert L.j3d_pool_fetch(pool.h, slots[i], out.ctypes.data, ctypes.byref(r), ctypes.byref(k)) == 0
+            say(f"fetched slot {slots[i]} {n}: {k.value} sweeps, residual {r.value!r}")
+            assert np.array_equal(out, want), i
+            assert r.value == want_r and k.value == want_k, i
+            if hosts[i] is not None:
+                assert np.array_equal(hosts[i].reshape(n[2], n[1], n[0]), want)
+            pool.release(slots[i])
+        assert specs[2][1] > want_k  # the third request stopped early at its tolerance
+        assert L.j3d_pool_fetch(pool.h, slots[0], None, None, None) == j3d.J3D_ESTATE  # released
+
+
 def test_pool_zero_iterations_returns_initial_grid(env):
     oracle, api, j3d, W = env
     with api.Pool(1 << 28, max_slots=2) as pool:

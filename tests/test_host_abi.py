@@ -195,3 +195,43 @@ def test_create_without_device_is_edevice():
     with pytest.raises(j3d.J3DError) as e:
         j3d.j3d_device_cus()
     assert e.value.status == j3d.J3D_EDEVICE
+
+
+def test_pool_entry_points_validate_before_device_work():
+    # every pool call rejects a NULL handle or bad arguments with EINVAL (or
+    # ENOMEM for a short arena) before it touches a device: none is present here
+    import ctypes
+    L = j3d._lib
+    i32, i64, dbl = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_double()
+    u64 = ctypes.c_uint64()
+    buf = (ctypes.c_double * 64)()
+    for fn, args in ((L.j3d_pool_fetch, (None, 0, buf, ctypes.byref(dbl), ctypes.byref(i64))),
+                     (L.j3d_pool_fetch, (None, 0, None, None, None)),
+                     (L.j3d_pool_result, (None, 0, ctypes.byref(dbl), ctypes.byref(i64))),
+                     (L.j3d_pool_admit, (None, None, 10, 0.0, 0, None, ctypes.byref(i32))),
+                     (L.j3d_pool_step, (None, 1)),
+                     (L.j3d_pool_poll, (None, None, 0, ctypes.byref(i32), None)),
+                     (L.j3d_pool_release, (None, 0)),
+                     (L.j3d_pool_usage, (None, None, None)),
+                     (L.j3d_pool_set_policy, (None, 0, 1, 0)),
+                     (L.j3d_pool_set_tune, (None, None)),
+                     (L.j3d_pool_destroy, (None,)),
+                     (L.j3d_pool_overhead_bytes, (0, ctypes.byref(u64))),
+                     (L.j3d_pool_overhead_bytes, (4, None))):
+        assert fn(*args) == j3d.J3D_EINVAL, fn.__name__
+    h = ctypes.c_void_p()
+    over = j3d.j3d_pool_overhead_bytes(4)
+    aligned, unaligned = 1 << 20, (1 << 20) + 8
+    cases = [((None, over + 4096, 4096, 4, None, ctypes.byref(h)), j3d.J3D_EINVAL),        # NULL arena
+             ((unaligned, over + 4096, 4096, 4, None, ctypes.byref(h)), j3d.J3D_EINVAL),   # unaligned
+             ((aligned, over + 4096, 4096, 0, None, ctypes.byref(h)), j3d.J3D_EINVAL),     # no slots
+             ((aligned, over + 4096, 0, 4, None, ctypes.byref(h)), j3d.J3D_EINVAL),        # no budget
+             ((aligned, over + 4095, 4096, 4, None, ctypes.byref(h)), j3d.J3D_ENOMEM),     # short arena
+             ((aligned, over + 4096, 4096, 4, None, None), j3d.J3D_EINVAL)]                # NULL out
+    for args, want in cases:
+        assert L.j3d_pool_create(*args) == want, args
+    assert not h.value  # no handle was made
+    # a decomposed problem is not a pool request
+    with pytest.raises(j3d.J3DError) as e:
+        j3d.j3d_pool_request_bytes(j3d.Problem((64, 64, 64), (2, 1, 1)))
+    assert e.value.status == j3d.J3D_EINVAL

@@ -302,6 +302,29 @@ def test_threads_do_not_change_bits(oracle_mod):
     assert np.array_equal(a, b) and ra == rb
 
 
+def test_host_tuned_timing_build_gives_the_same_bits(oracle_mod):
+    # The CPU baseline times a copy built with -O3 -march=native on the host
+    # it runs on; the parity build is portable.  Contraction stays off and no
+    # fast-math is set in either, so vector code must not change a bit:
+    # ragged grids, per-cell faces, subnormals and several threads.
+    rng = np.random.default_rng(11)
+    for n, t, thr in [((23, 17, 29), 13, 1), ((64, 9, 5), 20, 4), ((1, 1, 1), 380, 1), ((33, 40, 7), 7, 3)]:
+        bc = rng.uniform(-1, 1, 6)
+        u0 = np.ones((1, 1, 1)) if n == (1, 1, 1) else None
+        if n == (1, 1, 1):
+            bc = np.zeros(6)
+        a, ra, _ = oracle_mod.jacobi(n, t, bc=bc, u0=u0, seed=5, nthreads=thr)
+        b, rb, _ = oracle_mod.jacobi(n, t, bc=bc, u0=u0, seed=5, nthreads=thr, native=True)
+        assert a.tobytes() == b.tobytes() and np.float64(ra).tobytes() == np.float64(rb).tobytes()
+    nx, ny, nz = 19, 11, 6
+    faces = [rng.uniform(-1, 1, s) for s in [(nz, ny)] * 2 + [(nz, nx)] * 2 + [(ny, nx)] * 2]
+    a, ra, _ = oracle_mod.jacobi((nx, ny, nz), 9, faces=faces, seed=3, nthreads=2)
+    b, rb, _ = oracle_mod.jacobi((nx, ny, nz), 9, faces=faces, seed=3, nthreads=2, native=True)
+    assert a.tobytes() == b.tobytes() and ra == rb
+    out, _, _ = oracle_mod.jacobi((1, 1, 1), 380, u0=np.ones((1, 1, 1)), native=True)
+    assert 0.0 < float(out[0, 0, 0]) < 2.0 ** -1022  # denormals kept in the tuned build too
+
+
 def test_checked_run_stops_at_first_check_below_tol(oracle_mod):
     n = (12, 10, 8)
     res = {}
