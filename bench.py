@@ -8,9 +8,15 @@ step is a whole solve: reset the interior from a copy resident in HBM, then
 block, fused into one kernel and replayed from a HIP graph) with the residual
 of the last sweep.  value = interior cells x sweeps / step time (GLUP/s).
 
+The same line carries the rest of the metric under "configs", one compact
+record per workload: the 512^3 grid in the unfused and fused modes, the
+1024^3 grid at four decompositions, the batched form (256 problems) against
+a per-problem loop, and the served form (Poisson arrivals) against serial
+plain solves with p50/p99 latency (--headline-only skips them).
+
 Other workloads (--workload): modes, sweep (1024^3 decompositions), batch,
-serve; each prints its own JSON lines.  Multi-GPU runs are not part of this
-build: --gpus above 1 exits with a message.
+serve, odf, hostex, twostep; each prints its own JSON lines.  Multi-GPU runs
+are not part of this build: --gpus above 1 exits with a message.
 """
 from __future__ import annotations
 
@@ -68,24 +74,31 @@ def measured_traffic(edge, blocks):
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
-def copy_bandwidth(nbytes=2 << 30, reps=10):
-    """Measured streaming copy (read + write bytes per second), GB/s."""
+def copy_bandwidth(nbytes=2 << 30, reps=10, runtime=False):
+    """Measured streaming copy (read + write bytes per second), GB/s: the
+    library's copy kernel, and with runtime=True also the HIP runtime's own
+    device-to-device copy (hipMemcpyAsync, through torch's copy_) as a pair."""
     import torch
     from paper_2202_11819_amd import j3d
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
-    st = torch.cuda.current_stream().cuda_stream
-    j3d.j3d_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, st)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        j3d.j3d_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, st)
-    e1.record()
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    st = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        e1.synchronize()
+        return 2 * nbytes / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+
+    lib = timed(lambda: j3d.j3d_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, st.cuda_stream))
+    rt = timed(lambda: dst.copy_(src)) if runtime else None
     del src, dst
     torch.cuda.empty_cache()
-    return 2 * nbytes / (ms * 1e-3) / 1e9
+    return (lib, rt) if runtime else lib
 
 
 def cpu_baseline(n, target_seconds=15.0):
@@ -228,10 +241,12 @@ def bench_overdecomposed(args):
     s.close()
     del u0
     torch.cuda.empty_cache()
-    if not args.no_two_sweep:
-        out["undivided_two_sweep"] = two_sweep_side(n, sweeps)
+    if not args.headline_only:
+        out["configs"] = side_configs(args, spec)
     if not args.no_copy:
-        out["copy_GBps"] = round(copy_bandwidth(), 1)
+        lib_copy, rt_copy = copy_bandwidth(runtime=True)
+        out["copy_GBps"] = round(lib_copy, 1)
+        out["runtime_copy_GBps"] = round(rt_copy, 1)
         out["roofline"]["frac_of_copy"] = round(achieved / out["copy_GBps"], 4)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
@@ -239,28 +254,70 @@ def bench_overdecomposed(args):
     print(json.dumps(out), flush=True)
 
 
-def two_sweep_side(n, sweeps):
-    """The same grid left undivided, one sweep per launch (graph) against two
-    (TWO_SWEEP): a side measurement, not the benchmark's value."""
+def side_configs(args, spec):
+    """The rest of the metric, one compact record per configuration: the same
+    512^3 grid in the unfused and fused modes (and bit-identical to the
+    undivided run), the 1024^3 decomposition sweep, the batched form against a
+    per-problem loop, and the served form against serial plain solves."""
+    out = {}
+    log("[bench] config: modes of the overdecomposed grid")
+    out["overdecomposed_modes"] = modes_side(spec)
+    log("[bench] config: 1024^3 decompositions")
+    out["decompositions_1024"] = {"workload": "1024^3 FP64 grid, 500 sweeps (graph) per decomposition",
+                                  "runs": sweep_records(iters=args.sweep_iters)}
+    from paper_2202_11819_amd import serve
+    log("[bench] config: batched form")
+    b = serve.batch_bench(log=log)
+    out["batched"] = {k: b[k] for k in ("value", "unit", "batched_s", "tune", "tile", "autotune",
+                                       "per_problem_loop_s", "per_problem_loop_GLUPs", "speedup_vs_loop", "config")}
+    out["batched"]["hbm_frac"] = round(b["value"] * batch_bytes_per_lup() / HBM_PEAK_GBPS, 4)
+    log("[bench] config: served form")
+    sv = serve.serve_bench(count=args.requests, load=args.load, log=log)
+    out["served"] = {k: sv[k] for k in ("value", "unit", "pool", "serial_plain", "p99_vs_serial", "mix_vs_alone",
+                                       "config")}
+    return out
+
+
+def batch_bytes_per_lup():
+    """Algorithmic bytes per cell update of the batched workload (interior read
+    and write plus the Dirichlet halo reads, weighted by sweeps)."""
+    from paper_2202_11819_amd import workloads as W
+    lups = byts = 0
+    for s in W.batch():
+        nx, ny, nz = s.n
+        c = nx * ny * nz
+        lups += c * s.iters
+        byts += s.iters * (16 * c + 16 * (ny * nz + nx * nz + nx * ny))
+    return byts / lups
+
+
+def modes_side(spec):
+    """ms per sweep of the overdecomposed grid in the unfused modes (per block
+    and per phase), fused and graph; and whether the graph run equals the
+    undivided grid's bit for bit after the full sweep count."""
     import torch
     from paper_2202_11819_amd import api
-
+    n, sweeps = spec.n, spec.iters
     cells = n[0] * n[1] * n[2]
-    sweeps -= sweeps % 2
-    res = {"grid": list(n), "blocks": [1, 1, 1], "sweeps": sweeps}
-    with api.Solver(n, seed=1) as s:
-        for mode, key in (("graph", "one_sweep_GLUPs"), ("two_sweep", "two_sweep_GLUPs")):
-            s.run(10, mode=mode)
+    res = {"workload": f"{n[0]}^3 as {spec.nblk[0]}x{spec.nblk[1]}x{spec.nblk[2]} blocks", "ms_per_sweep": {}}
+    for mode, iters in (("unfused_block", 6), ("unfused_phase", 100), ("fused", sweeps), ("graph", sweeps)):
+        with api.Solver(n, nblk=spec.nblk, seed=spec.seed) as s:
+            s.run(2, mode=mode)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            s.run(sweeps, mode=mode)
-            e1.record()
+            e0.record(s.stream)
+            s.run(iters, mode=mode)
+            e1.record(s.stream)
             e1.synchronize()
-            ms = e0.elapsed_time(e1)
-            res[key] = round(cells * sweeps / ms / 1e6, 2)
-            if mode == "two_sweep":
-                res["two_sweep_launch_ms"] = round(2 * ms / sweeps, 4)
+            ms = e0.elapsed_time(e1) / iters
+            res["ms_per_sweep"][mode] = round(ms, 4)
+            res.setdefault("GLUPs", {})[mode] = round(cells / ms / 1e6, 2)
+    with api.Solver(n, nblk=spec.nblk, seed=spec.seed) as a, api.Solver(n, seed=spec.seed) as b:
+        a.run(sweeps, mode="graph")
+        b.run(sweeps, mode="graph")
+        ua, ub = a.get_interior_device(), b.get_interior_device()
+        res["graph_equals_undivided_bitwise"] = bool(torch.equal(ua.view(torch.int64), ub.view(torch.int64)))
+        del ua, ub
     torch.cuda.empty_cache()
     return res
 
@@ -295,35 +352,42 @@ def bench_modes(args):
         torch.cuda.empty_cache()
 
 
-def bench_sweep(args):
-    """1024^3 at several decompositions: GLUP/s and effective GB/s vs block count."""
+def sweep_records(iters=500):
+    """1024^3 at several decompositions: GLUP/s and algorithmic GB/s vs block count."""
     import torch
     from paper_2202_11819_amd import api, j3d
     from paper_2202_11819_amd import workloads as W
 
-    for label, spec in W.block_sweep(iters=args.sweep_iters):
+    recs = []
+    for label, spec in W.block_sweep(iters=iters):
         n = spec.n
         cells = n[0] * n[1] * n[2]
         s = api.Solver(n, nblk=spec.nblk, split=spec.split, seed=spec.seed)
         s.run(10, mode="graph")
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
+        e0.record(s.stream)
         s.run(spec.iters, mode="graph")
-        e1.record()
+        e1.record(s.stream)
         e1.synchronize()
         ms = e0.elapsed_time(e1)
         per = sweep_bytes(s.problem)
         gbps = per * spec.iters / (ms * 1e-3) / 1e9
         nblocks = spec.nblk[0] * spec.nblk[1] * spec.nblk[2]
-        print(json.dumps({"metric": "FP64 Jacobi3D GLUP/s vs decomposition", "workload": label,
-                          "blocks": nblocks, "value": round(cells * spec.iters / ms / 1e6, 3), "unit": "GLUP/s",
-                          "GBps": round(gbps, 1), "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4),
-                          "B_per_LUP": round(per / cells, 3), "sweeps": spec.iters,
-                          "ms_per_sweep": round(ms / spec.iters, 4), "tune": list(s.get_tune()),
-                          "tile": list(j3d.variants()[s.get_tune()[0]])}), flush=True)
+        recs.append({"workload": label, "blocks": nblocks, "value": round(cells * spec.iters / ms / 1e6, 3),
+                     "unit": "GLUP/s", "GBps": round(gbps, 1), "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4),
+                     "B_per_LUP": round(per / cells, 3), "sweeps": spec.iters,
+                     "ms_per_sweep": round(ms / spec.iters, 4), "tune": list(s.get_tune()),
+                     "tile": list(j3d.variants()[s.get_tune()[0]])})
         s.close()
         torch.cuda.empty_cache()
+    return recs
+
+
+def bench_sweep(args):
+    for r in sweep_records(iters=args.sweep_iters):
+        r["metric"] = "FP64 Jacobi3D GLUP/s vs decomposition"
+        print(json.dumps(r), flush=True)
     if not args.no_copy:  # the copy kernel of known size also calibrates counter runs of this workload
         print(json.dumps({"metric": "streaming copy, 2 GiB", "copy_GBps": round(copy_bandwidth(), 1)}), flush=True)
 
@@ -439,7 +503,9 @@ def main():
     ap.add_argument("--tune", default="", help="variant,zchunk,blocks_per_cu")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
-    ap.add_argument("--no-two-sweep", action="store_true", help="skip the undivided two-sweep side measurement")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="default workload: only the 512^3 line (no modes, decompositions, batched or served records)")
+    ap.add_argument("--batch-two-sweep", action="store_true", help="batch workload: also two sweeps per launch")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--requests", type=int, default=1100, help="serve workload: number of requests")
     ap.add_argument("--serve-dump", default="", help="serve workload: write per-request records here")

@@ -38,14 +38,18 @@ def device_arch() -> str:
 
 
 def candidates(problems):
-    """Tile shapes that suit the mix's widths, crossed with z-chunks and schedules."""
+    """Stage 1: every tile shape that suits the mix's widths, z-chunk 32, one
+    workgroup per tile."""
     widest = max(p.n[0] for p in problems)
+    return [(v, 32, 0) for v, (tx, ty, threads) in enumerate(j3d.variants()) if tx <= max(64, 2 * widest)]
+
+
+def refinements(best_shapes):
+    """Stage 2: the best shapes of stage 1 crossed with z-chunks and schedules."""
     out = []
-    for v, (tx, ty, threads) in enumerate(j3d.variants()):
-        if tx > max(64, 2 * widest):
-            continue
-        for zc in (0, 32, 64):
-            for bpc in (0, 2, 4):
+    for v in best_shapes:
+        for zc in (0, 16, 24, 32, 48, 64):
+            for bpc in (0, 2):
                 out.append((v, zc, bpc))
     return out
 
@@ -65,8 +69,12 @@ def time_batch(problems, iters, tune, stream=None) -> float:
         b.close()
 
 
-def tune_batch(problems, iters, sample_sweeps=24, cache_path=DEFAULT_CACHE, log=None, force=False):
-    """Best (variant, zchunk, blocks_per_cu) for this mix; cached per (arch, size class)."""
+def tune_batch(problems, iters, sample_sweeps=24, cache_path=DEFAULT_CACHE, log=None, force=False,
+               report=False, keep=3):
+    """Best (variant, zchunk, blocks_per_cu) for this mix; cached per (arch, size class).
+    Two stages on a shortened copy of the mix: every suitable tile shape at
+    z-chunk 32, then the `keep` best shapes over z-chunks and schedules.
+    report=True returns (tune, candidates timed), 0 timed for a cache hit."""
     # the key names the library build and its tile table, so a cache written
     # by another build (whose variant indices may mean other shapes) is not used
     table = hashlib.sha256(repr(j3d.variants()).encode()).hexdigest()[:12]
@@ -76,23 +84,31 @@ def tune_batch(problems, iters, sample_sweeps=24, cache_path=DEFAULT_CACHE, log=
         with open(cache_path) as f:
             cache = json.load(f)
     if not force and key in cache:
-        return tuple(cache[key]["tune"])
+        best = tuple(cache[key]["tune"])
+        return (best, 0) if report else best
     # a shortened copy of the mix keeps the same tiles and the same
     # relative iteration counts
     top = max(iters) if iters else 1
     short = [max(1, round(sample_sweeps * it / top)) if it > 0 else 0 for it in iters]
-    results = []
     t0 = time.perf_counter()
-    for cand in candidates(problems):
-        try:
-            dt = time_batch(problems, short, cand)
-        except j3d.J3DError:
-            continue
-        results.append((dt, cand))
-        if log:
-            log(f"[autotune] variant {cand[0]} {j3d.variants()[cand[0]]} zchunk {cand[1]} "
-                f"blocks/CU {cand[2]}: {dt * 1e3:.2f} ms")
-    results.sort()
+
+    def run(cands):
+        res = []
+        for cand in cands:
+            try:
+                dt = time_batch(problems, short, cand)
+            except j3d.J3DError:
+                continue
+            res.append((dt, cand))
+            if log:
+                log(f"[autotune] variant {cand[0]} {j3d.variants()[cand[0]]} zchunk {cand[1]} "
+                    f"blocks/CU {cand[2]}: {dt * 1e3:.2f} ms")
+        return sorted(res)
+
+    stage1 = run(candidates(problems))
+    shapes = [c[0] for _, c in stage1[:keep]]
+    stage2 = run([c for c in refinements(shapes) if c[1] != 32 or c[2] != 0])
+    results = sorted(stage1 + stage2)
     best = results[0][1]
     cache[key] = {"tune": list(best), "seconds": results[0][0], "searched": len(results),
                   "search_s": round(time.perf_counter() - t0, 2)}
@@ -100,4 +116,4 @@ def tune_batch(problems, iters, sample_sweeps=24, cache_path=DEFAULT_CACHE, log=
         os.makedirs(os.path.dirname(cache_path), exist_ok=True)
         with open(cache_path, "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)
-    return best
+    return (best, len(results)) if report else best

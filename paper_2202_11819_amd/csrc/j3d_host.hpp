@@ -96,10 +96,13 @@ inline void tiles_xy(const VariantInfo &vi, int64_t ex, int64_t ey, int64_t *ntx
 // Validates a tune against a plan; fills the effective z-chunk.
 j3d_status check_tune(const Plan &plan, const j3d_tune *t, int *zchunk_eff);
 
-// Row stride of a block's field in doubles: rows start on 128-byte lines.
-inline int64_t row_pitch(int64_t ex) { return ex >= 16 ? (ex + 15) / 16 * 16 : ex; }
+// Row stride of a block's field in doubles: rows are stored unpadded, so the
+// rows of a plane form one contiguous run and a tile of whole rows reads and
+// writes one run per plane (no padding bytes move, no line is half used
+// except where two tiles meet).
+inline int64_t row_pitch(int64_t ex) { return ex; }
 
-// Cells of one block's field (one parity), halos and row padding included.
+// Cells of one block's field (one parity), halos included.
 inline int64_t block_field_cells(int64_t ex, int64_t ey, int64_t ez)
 {
     return row_pitch(ex) * (ey + 2) * (ez + 2);

@@ -5,13 +5,12 @@
 // swaps their roles every iteration):
 //
 //   field  F[p][b]: (ez+2) planes x (ey+2) rows x pitch doubles, x fastest,
-//          pitch = ex rounded up to a multiple of 16 (a 128-byte cache line)
-//          when ex >= 16, else ex.  Plane 0 and plane ez+1 hold the z- / z+
-//          halos, row 0 and row ey+1 of every plane hold the y- / y+ halos;
-//          interior cell (x, y, z) sits at ((z+1)*(ey+2) + (y+1))*pitch + x.
-//          Rows carry no x ghosts, so a row of the interior and a y- or z-halo
-//          row are the same contiguous ex doubles; edge rows of the halo
-//          planes and the row padding are never read.
+//          pitch = ex (rows unpadded: a plane is one contiguous run).  Plane 0
+//          and plane ez+1 hold the z- / z+ halos, row 0 and row ey+1 of every
+//          plane hold the y- / y+ halos; interior cell (x, y, z) sits at
+//          ((z+1)*(ey+2) + (y+1))*pitch + x.  Rows carry no x ghosts, so a row
+//          of the interior and a y- or z-halo row are the same contiguous ex
+//          doubles; edge rows of the halo planes are never read.
 //   x-halo X[p][b]: two arrays of ey*ez doubles (x- then x+), y fastest.  The
 //          x-halos live apart from the rows so that a neighbour writes them as
 //          contiguous runs instead of one double per row.
@@ -43,7 +42,7 @@ struct BlockDesc {          // 128 bytes, read by kernels through scalar loads
     int32_t prob;           // index of the owning problem in the problem table
     int32_t nbr[6];         // neighbour block per face (table index) or -1
     int32_t org[3];         // global coordinates of the block's first cell
-    int32_t pitch;          // row stride of the field in doubles: ex rounded up to 16 (128 B)
+    int32_t pitch;          // row stride of the field in doubles (= ex: rows unpadded)
     int32_t pad[6];
 };
 static_assert(sizeof(BlockDesc) == 128, "BlockDesc layout");
@@ -71,7 +70,9 @@ enum : int32_t {
     SW_FUSED = 1,   // halos from the neighbours (y, z read directly; x faces handed over)
     SW_RES = 2,     // plain mode: residual of this sweep into res[0] (via the block's problem)
     SW_MULTI = 4,   // per-problem activity, parity and residual policy from ProbDesc
-    SW_PERSIST = 8  // persistent grid with per-XCD tile queues
+    SW_PERSIST = 8, // persistent grid with per-XCD tile queues
+    SW_INNER = 16   // only the cells whose six neighbours lie inside the block (Fig. 1's
+                    // interior update): every tile clipped to [1, e-1) on each axis
 };
 
 struct SweepArgs {
@@ -103,27 +104,33 @@ int variant_count();
 VariantInfo variant_info(int v);
 
 // ---- flattened tiles ------------------------------------------------------------
-// A flattened tile covers nxv x nyv cells of an x-y plane.  Its rows are dealt
-// to the threads in order, each row padded to a multiple of 16 lanes (one
-// 128-byte line of doubles), so a row starts on a line boundary in memory and
-// on a 16-lane boundary in the wave, and at most 15 lanes per row idle whatever
-// the block's width.  Per block, x is cut into tnx pieces of at most
-// flat_max_x(nt) columns (each after the first starting on a 16-column
-// boundary) and y into tny near-equal pieces of at most hy rows, with
-// pad16(wx) * hy <= cap (cells per thread budget) and 2 * (wx + hy) <= nt (one
-// thread per cell of the tile's halo ring), wx being the widest x piece.  Host
-// and kernels evaluate the same functions.
+// A flattened tile covers nxv x nyv cells of an x-y plane.  Its cells are
+// numbered x fastest and dealt to the threads in order (slot f is cell
+// (f % nxv, f / nxv)), so no lane idles except in the tile's last partial
+// wave.  Rows are stored unpadded (pitch = width), so a tile of whole rows is
+// one contiguous run of memory per plane: consecutive lanes read and write
+// consecutive doubles, and only the run's two end lines are shared with the
+// neighbouring tiles.  Per block the tile covers whole rows, hy of them with
+// ex * hy <= cap (cells per thread budget), as long as the halo ring still has
+// one loader thread per cell with that many rows (2 * (ex + hy) <= nt).
+// Wider blocks are cut into tnx pieces of at most flat_max_x(nt) columns (each
+// after the first starting on a 16-column boundary) and y into tny near-equal
+// pieces of at most hy rows, with wx * hy <= cap and 2 * (wx + hy) <= nt, wx
+// being the widest x piece.  Host and kernels evaluate the same functions.
 struct FlatShape {
     int tnx, tny, wx, hy;
 };
-constexpr int pad16(int x) { return (x + 15) / 16 * 16; }
 constexpr int flat_max_x(int nt) { return nt >= 512 ? 192 : nt / 2 - 32; }
 constexpr FlatShape flat_shape(int ex, int ey, int nt, int cap)
 {
-    const int mx = flat_max_x(nt);
-    const int tnx = (ex + mx - 1) / mx;
-    const int wx = tnx == 1 ? ex : (ex + tnx - 1) / tnx + 15;
-    int hy = cap / pad16(wx);
+    int tnx = 1, wx = ex;
+    const int rows = cap / ex < ey ? cap / ex : ey;
+    if (rows < 1 || nt / 2 - ex < rows) {  // the ring would limit whole rows: cut x
+        const int mx = flat_max_x(nt);
+        tnx = (ex + mx - 1) / mx;
+        wx = tnx == 1 ? ex : (ex + tnx - 1) / tnx + 15;
+    }
+    int hy = cap / wx;
     if (nt / 2 - wx < hy) hy = nt / 2 - wx;
     if (ey < hy) hy = ey;
     if (hy < 1) hy = 1;

@@ -166,11 +166,10 @@ struct Tiled {
     __device__ static int lx(int) { return LXC; }
     __device__ static bool full(int nxv, int nyv) { return nxv == TX && nyv == TY; }
     template <bool FULL>
-    __device__ static bool cell(int tid, int r, int nxv, int nyv, bool, int &cx, int &cy, bool &pad)
+    __device__ static bool cell(int tid, int r, int nxv, int nyv, int &cx, int &cy)
     {
         cx = tid % TX;
         cy = tid / TX + NTY * r;
-        pad = false;
         return FULL || (cx < nxv && cy < nyv);
     }
     // ring cell of this thread: kind 0/1 = y-/y+ row (c = column), 2/3 = x-/x+ column (c = row)
@@ -196,11 +195,11 @@ struct Tiled {
     }
 };
 
-// Flattened tiles: the rectangle's rows, each padded to w = pad16(nxv) lanes,
-// are numbered x fastest and slot f goes to thread f % NT, row f / NT; the
-// rectangle is sized per block by flat_shape, so only the padding lanes of a
-// row and those of the last partial wave idle, and every row segment starts on
-// a cache line.
+// Flattened tiles: the rectangle's cells, numbered x fastest, are dealt to
+// the threads in order (slot f goes to thread f % NT, row f / NT); the
+// rectangle is sized per block by flat_shape, so only the lanes of the last
+// partial wave idle.  With whole rows (the usual case) a plane of the tile is
+// one contiguous run of memory and every wave reads 64 consecutive doubles.
 template <int NT_, int RY_, int PF_>
 struct Flat {
     static constexpr int NT = NT_, RY = RY_, PF = PF_;
@@ -213,20 +212,16 @@ struct Flat {
     static_assert(NT % 64 == 0 && NT >= 256, "whole waves, room for a halo ring");
     static_assert(PF >= 1 && PF <= 4, "prefetch depth");
     __device__ static int lx(int nxv) { return nxv + 2; }
-    // every slot of every thread holds a cell (no padding lane, no idle tail)
-    __device__ static bool full(int nxv, int nyv) { return nxv % 16 == 0 && nxv * nyv == CAP; }
-    // pad: the slot is a padding lane of a row whose padding exists in memory
-    // (padok: the tile ends where the field's row padding starts)
+    // every slot of every thread holds a cell (no idle tail)
+    __device__ static bool full(int nxv, int nyv) { return nxv * nyv == CAP; }
     template <bool FULL>
-    __device__ static bool cell(int tid, int r, int nxv, int nyv, bool padok, int &cx, int &cy, bool &pad)
+    __device__ static bool cell(int tid, int r, int nxv, int nyv, int &cx, int &cy)
     {
-        const int w = pad16(nxv);
         const int f = tid + r * NT;
-        const int q = f / w, x = f - q * w;
-        const bool v = q < nyv && x < nxv;
-        pad = padok && q < nyv && x >= nxv;
-        cy = v || pad ? q : 0;
-        cx = v || pad ? x : 0;
+        const int q = f / nxv, x = f - q * nxv;
+        const bool v = FULL || q < nyv;
+        cy = v ? q : 0;
+        cx = v ? x : 0;
         return v;
     }
     __device__ static bool ring(int tid, int nxv, int nyv, int &kind, int &c)
@@ -267,7 +262,7 @@ template <class K, bool FULL>
 __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *__restrict__ hsrc0,
                                                uint64_t hstep, int hl, double *sm, double *xf)
 {
-    constexpr int RY = K::RY, NT = K::NT;
+    constexpr int RY = K::RY;
     // Register ring of NB planes: while plane k is computed from planes
     // k-1, k, k+1, the loads of planes k+2 .. k+1+PF are in flight.  The loop
     // is unrolled NB times so every ring index is a compile-time constant and
@@ -290,22 +285,16 @@ __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *_
     // their LDS reads to a valid cell.
     constexpr uint32_t kOutside = 0x80000000u;
     bool vr[RY];
-    bool pd[RY];       // slot on the row padding after the tile's last column: it
-                       // stores back the value it loaded, so rows are written as
-                       // whole cache lines (no partial-line writes at row ends)
     uint32_t off[RY];  // byte offset of this thread's cell of row r inside a plane
     int lw[RY];        // LDS slot this thread writes for row r
     int li[RY];        // LDS slot of the cell (its four in-plane neighbours are +-1, +-lx)
     int ly[RY];        // row of the cell inside the tile
     bool fxm[RY], fxp[RY];  // cell on the block's x- / x+ face with a neighbour there (fused)
-    const bool padok = g.x0 + pad16(g.nxv) <= g.pitch;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         int cx, cy;
-        bool pad;
-        vr[r] = K::template cell<FULL>(tid, r, g.nxv, g.nyv, padok, cx, cy, pad);
-        pd[r] = pad;
-        off[r] = vr[r] || pad ? (uint32_t)(g.y0 + cy + 1) * rowb + (uint32_t)(g.x0 + cx) * 8u : kOutside;
+        vr[r] = K::template cell<FULL>(tid, r, g.nxv, g.nyv, cx, cy);
+        off[r] = vr[r] ? (uint32_t)(g.y0 + cy + 1) * rowb + (uint32_t)(g.x0 + cx) * 8u : kOutside;
         li[r] = vr[r] ? (cy + 1) * lx + cx + 1 : lx + 1;
         lw[r] = vr[r] ? li[r] : K::SINK + (tid & 63);
         ly[r] = cy;
@@ -373,7 +362,7 @@ __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *_
             s += R[jm][r];
             s += R[jp][r];
             const double v = s * kW;
-            bstore<kAuxStore>(ro, off[r], pd[r] ? R[jc][r] : v);
+            bstore<kAuxStore>(ro, off[r], v);
             if (fxm[r]) XF[ly[r]] = v;
             if (fxp[r]) XF[K::XROWS + ly[r]] = v;
             if (g.want_res) {
@@ -446,6 +435,18 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
         const int ntz = (ez + a.zchunk - 1) / a.zchunk;
         g.z0 = (int)((int64_t)tl.tz * ez / ntz);
         g.nzv = (int)((int64_t)(tl.tz + 1) * ez / ntz) - g.z0;
+    }
+    if (a.flags & SW_INNER) {
+        // Fig. 1's interior update: the cells that read no halo, i.e. the tile
+        // clipped to [1, e-1) along every axis (uniform over the workgroup)
+        const int x1 = min(g.x0 + g.nxv, ex - 1), y1 = min(g.y0 + g.nyv, ey - 1), z1 = min(g.z0 + g.nzv, ez - 1);
+        g.x0 = max(g.x0, 1);
+        g.y0 = max(g.y0, 1);
+        g.z0 = max(g.z0, 1);
+        g.nxv = x1 - g.x0;
+        g.nyv = y1 - g.y0;
+        g.nzv = z1 - g.z0;
+        if (g.nxv <= 0 || g.nyv <= 0 || g.nzv <= 0) return;
     }
 
     // Halo sources.  The unfused sweep reads the block's own ghost layer,
@@ -786,7 +787,7 @@ __global__ __launch_bounds__(256) void init_kernel(double *base, const BlockDesc
     const double qnan = __builtin_nan("");
     for (int bb = blockIdx.y; bb < nblocks; bb += gridDim.y) {
         const BlockDesc &B = blocks[block_begin + bb];
-        const int ex = B.ext[0], ey = B.ext[1], ez = B.ext[2], pitch = B.pitch;
+        const int ey = B.ext[1], ez = B.ext[2], pitch = B.pitch;
         const int64_t cells = (int64_t)pitch * (ey + 2) * (ez + 2);
         double *F0 = base + B.off[0];
         double *F1 = base + B.off[1];
@@ -795,11 +796,6 @@ __global__ __launch_bounds__(256) void init_kernel(double *base, const BlockDesc
         for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < cells; idx += stride) {
             const int x = (int)(idx % pitch);
             const int64_t rr = idx / pitch;
-            if (x >= ex) {  // row padding: never read as data
-                F0[idx] = 0.0;
-                F1[idx] = 0.0;
-                continue;
-            }
             const int yy = (int)(rr % (ey + 2)), zz = (int)(rr / (ey + 2));
             const bool oy = (yy == 0 || yy == ey + 1), oz = (zz == 0 || zz == ez + 1);
             if (!oy && !oz) {

@@ -273,13 +273,15 @@ j3d_status sweep(j3d_solver *s, int parity, bool fused, bool res, int32_t t0, in
 }
 
 // One workgroup per tile, whatever the tune's schedule (per-block launches).
-j3d_status sweep_tiles(j3d_solver *s, int parity, bool fused, bool res, int32_t t0, int32_t cnt, hipStream_t st)
+// extra_flags: SW_INNER restricts the sweep to the cells that read no halo.
+j3d_status sweep_tiles(j3d_solver *s, int parity, bool fused, bool res, int32_t t0, int32_t cnt, hipStream_t st,
+                       int32_t extra_flags = 0)
 {
     SweepArgs a = base_args(s);
     a.tile_begin = t0;
     a.tile_count = cnt;
     a.parity = parity;
-    a.flags = (fused ? SW_FUSED : 0) | (res ? SW_RES : 0);
+    a.flags = (fused ? SW_FUSED : 0) | (res ? SW_RES : 0) | extra_flags;
     return hip_status(launch_sweep(s->tune.variant, a, cnt, st), "sweep launch");
 }
 
@@ -513,7 +515,8 @@ j3d_status run_host_staged(j3d_solver *s, int p, bool res, bool overlap, hipStre
     if (overlap) {
         st = ensure_side_streams(s);
         if (st == J3D_OK) st = fork_side(s, main);
-        if (st == J3D_OK) st = sweep_tiles(s, p, false, false, 0, s->ntiles, s->side[0]);
+        // the interior update (cells that read no halo) while the faces travel
+        if (st == J3D_OK) st = sweep_tiles(s, p, false, false, 0, s->ntiles, s->side[0], SW_INNER);
         if (st != J3D_OK) return st;
     }
     st = hip_status(launch_pack(base, blocks, 0, nb, plan.max_face, p, 0x3f, main), "pack launch");

@@ -149,12 +149,14 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def bench_serve(args):
-    """Served workload: Poisson arrivals at `load` (default 0.8) x the serial capacity."""
-    count = int(getattr(args, "requests", 0) or 1100)
+def serve_bench(count=1100, load=0.8, tol=0.0, fill_cells=None, backlog_share=None, pool_tune=None,
+                pool_two_sweep=False, serial_two_sweep=False, dump="", log=_log):
+    """Served workload: Poisson arrivals at `load` x the serial capacity, served
+    by the pool and, on the same trace, one request at a time by plain solves.
+    Returns the benchmark record (a dict)."""
     warmup = min(100, count // 10)
     base = W.serve_trace(count=count, rate=1.0)
-    smode = "two_sweep" if getattr(args, "serial_two_sweep", False) else "graph"
+    smode = "two_sweep" if serial_two_sweep else "graph"
     # serial capacity from a sample of the same request mix, after a few
     # untimed solves (first-call costs are not part of the service time)
     serve_serial(W.rescale_arrivals(base[-5:], 1e9), mode=smode)
@@ -162,22 +164,15 @@ def bench_serve(args):
     t0 = time.perf_counter()
     serve_serial(W.rescale_arrivals(sample, 1e9), mode=smode)
     mean_service = (time.perf_counter() - t0) / len(sample)
-    load = float(getattr(args, "load", 0.8) or 0.8)
     rate = load / mean_service
     trace = W.rescale_arrivals(base, rate)
-    _log(f"[serve] mean serial service {mean_service * 1e3:.1f} ms -> arrival rate {rate:.2f}/s ({load} x capacity)")
+    log(f"[serve] mean serial service {mean_service * 1e3:.1f} ms -> arrival rate {rate:.2f}/s ({load} x capacity)")
     free = torch.cuda.mem_get_info()[0]
     budget = int(min(200e9, 0.85 * free))
-    fill = int(getattr(args, "fill_cells", -1))
-    share = int(getattr(args, "backlog_share", -1))
-    ptune = getattr(args, "pool_tune", "")
-    ptune = tuple(int(v) for v in ptune.split(",")) if ptune else None
-    tol = float(getattr(args, "tol", 0.0) or 0.0)
-    two = bool(getattr(args, "pool_two_sweep", False))
-    recs, rounds = serve_pool(trace, budget, log=_log, fill_cells=None if fill < 0 else fill, tune=ptune,
-                              backlog_share=None if share < 0 else share, tol=tol, two_sweep=two)
+    recs, rounds = serve_pool(trace, budget, log=log, fill_cells=fill_cells, tune=pool_tune,
+                              backlog_share=backlog_share, tol=tol, two_sweep=pool_two_sweep)
     pool_sum = summarize(recs, warmup)
-    srecs = serve_serial(trace, log=_log, tol=tol, mode=smode)
+    srecs = serve_serial(trace, log=log, tol=tol, mode=smode)
     serial_sum = summarize(srecs, warmup)
     # every request served in the mix against the same request solved alone:
     # the last sweep's residual (bit pattern) and the sweep count must agree
@@ -185,84 +180,107 @@ def bench_serve(args):
                    if np.float64(a["residual"]).tobytes() == np.float64(b["residual"]).tobytes())
     same_it = sum(1 for a, b in zip(recs, srecs) if a["iters"] == b["iters"])
     early = sum(1 for a, r in zip(recs, trace) if a["iters"] < r.spec.iters)
-    dump = getattr(args, "serve_dump", "")
     if dump:
         with open(dump, "w") as f:
             json.dump({"rate": rate, "pool": recs, "serial": srecs,
                        "specs": [[list(r.spec.n), r.spec.iters] for r in trace]}, f)
-    out = {"metric": "served solves/s and p50/p99 latency (arrival to result on host)",
-           "value": pool_sum["solves_per_s"], "unit": "solves/s", "higher_is_better": True,
-           "pool": pool_sum, "serial_plain": serial_sum, "rounds": rounds, "fill_cells": fill,
-           "mix_vs_alone": {"requests": len(recs), "residual_bit_identical": same_res,
-                            "sweeps_identical": same_it, "stopped_early": early},
-           "backlog_share": share, "pool_two_sweep": two, "serial_mode": smode,
-           "pool_tune": list(ptune) if ptune else None,
-           "config": {"workload": f"{count} Jacobi3D solve requests, Poisson arrivals at {rate:.2f}/s "
-                                  f"({load} x serial capacity), per-axis size U{{32..384}}, 50..2000 sweeps, "
-                                  f"residual every 50, tol {tol:g}, budget {budget / 1e9:.0f} GB, "
-                                  f"first {warmup} discarded", "dtype": "f64"}}
+    return {"metric": "served solves/s and p50/p99 latency (arrival to result on host)",
+            "value": pool_sum["solves_per_s"], "unit": "solves/s", "higher_is_better": True,
+            "pool": pool_sum, "serial_plain": serial_sum, "rounds": rounds,
+            "p99_vs_serial": round(serial_sum["p99_ms"] / pool_sum["p99_ms"], 3),
+            "mix_vs_alone": {"requests": len(recs), "residual_bit_identical": same_res,
+                             "sweeps_identical": same_it, "stopped_early": early},
+            "pool_two_sweep": pool_two_sweep, "serial_mode": smode,
+            "pool_tune": list(pool_tune) if pool_tune else None,
+            "config": {"workload": f"{count} Jacobi3D solve requests, Poisson arrivals at {rate:.2f}/s "
+                                   f"({load} x serial capacity), per-axis size U{{32..384}}, 50..2000 sweeps, "
+                                   f"residual every 50, tol {tol:g}, budget {budget / 1e9:.0f} GB, "
+                                   f"first {warmup} discarded", "dtype": "f64"}}
+
+
+def bench_serve(args):
+    fill = int(getattr(args, "fill_cells", -1))
+    share = int(getattr(args, "backlog_share", -1))
+    ptune = getattr(args, "pool_tune", "")
+    out = serve_bench(count=int(getattr(args, "requests", 0) or 1100), load=float(getattr(args, "load", 0.8) or 0.8),
+                      tol=float(getattr(args, "tol", 0.0) or 0.0), fill_cells=None if fill < 0 else fill,
+                      backlog_share=None if share < 0 else share,
+                      pool_tune=tuple(int(v) for v in ptune.split(",")) if ptune else None,
+                      pool_two_sweep=bool(getattr(args, "pool_two_sweep", False)),
+                      serial_two_sweep=bool(getattr(args, "serial_two_sweep", False)),
+                      dump=getattr(args, "serve_dump", ""))
     print(json.dumps(out), flush=True)
 
 
-def bench_batch(args):
-    """Batched workload: 256 problems in one launch per sweep vs a per-problem loop."""
+def batch_bench(tune=None, retune=False, batch_only=False, two_sweep=False, loop=True, log=_log):
+    """Batched workload: 256 problems in one launch per sweep (autotuned shape,
+    or `tune`) against the same problems solved one after another with the
+    plain solver.  Returns the benchmark record (a dict)."""
     from .autotune import tune_batch
 
     specs = W.batch()
     problems = [W.to_problem(s) for s in specs]
     iters = [s.iters for s in specs]
     lups = sum(p.cells * it for p, it in zip(problems, iters))
-    fixed = getattr(args, "tune", "")
-    if fixed:
-        tune = tuple(int(v) for v in fixed.split(","))
-    else:
-        tune = tune_batch(problems, iters, log=_log, force=getattr(args, "retune", False))
-    _log(f"[batch] tune {tune} ({j3d.variants()[tune[0]]})")
+    search = None
+    if tune is None:
+        t0 = time.perf_counter()
+        tune, searched = tune_batch(problems, iters, log=log, force=retune, report=True)
+        search = {"candidates": searched, "seconds": round(time.perf_counter() - t0, 2)}
+    tune = tuple(tune)
+    log(f"[batch] tune {tune} ({j3d.variants()[tune[0]]})")
 
-    def timed_batch(t, two_sweep=False):
+    def timed_batch(t, two=False):
         b = Batch(problems, iters, tune=t)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        b.run(residuals=False, two_sweep=two_sweep)
-        e1.record()
+        e0.record(b.stream)
+        b.run(residuals=False, two_sweep=two)
+        e1.record(b.stream)
         e1.synchronize()
         b.close()
         return e0.elapsed_time(e1) * 1e-3
 
     timed_batch(tune)
     tb = min(timed_batch(tune) for _ in range(2))
-    if getattr(args, "batch_only", False):
-        print(json.dumps({"metric": "batched FP64 Jacobi3D GLUP/s (256 problems, one launch per sweep)",
-                          "value": round(lups / tb / 1e9, 2), "unit": "GLUP/s", "batched_s": round(tb, 4),
-                          "tune": list(tune), "tile": list(j3d.variants()[tune[0]])}), flush=True)
-        return
-    tdef = timed_batch(None)
-    # the same batch with two sweeps per launch (all problems are undivided)
-    timed_batch(tune, True)
-    t2 = min(timed_batch(tune, True) for _ in range(2))
-    # per-problem loop: each problem solved on its own with the plain solver
-    run_s = 0.0
-    wall0 = time.perf_counter()
-    for s in specs:
-        sol = Solver(s.n, bc=s.bc, seed=s.seed, pid=s.pid)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        sol.run(s.iters, mode="graph")
-        e1.record()
-        e1.synchronize()
-        run_s += e0.elapsed_time(e1) * 1e-3
-        sol.close()
-    wall = time.perf_counter() - wall0
     out = {"metric": "batched FP64 Jacobi3D GLUP/s (256 problems, one launch per sweep)",
            "value": round(lups / tb / 1e9, 2), "unit": "GLUP/s", "higher_is_better": True,
-           "batched_s": round(tb, 4), "batched_default_tune_s": round(tdef, 4),
-           "two_sweep_batched_s": round(t2, 4), "two_sweep_GLUPs": round(lups / t2 / 1e9, 2),
-           "per_problem_loop_s": round(run_s, 4), "per_problem_loop_GLUPs": round(lups / run_s / 1e9, 2),
-           "per_problem_loop_wall_s": round(wall, 2), "speedup_vs_loop": round(run_s / tb, 3),
-           "tune": list(tune), "tile": list(j3d.variants()[tune[0]]),
+           "batched_s": round(tb, 4), "tune": list(tune), "tile": list(j3d.variants()[tune[0]]),
+           "autotune": search,
            "config": {"workload": f"256 independent problems, per-axis size log-uniform in [32, 256], "
                                   f"per-face bc U[-1,1], 100..1000 sweeps, {lups / 1e9:.1f} GLUP in total",
                       "dtype": "f64"}}
+    if batch_only:
+        return out
+    if two_sweep:
+        # the same batch with two sweeps per launch (all problems are undivided)
+        timed_batch(tune, True)
+        t2 = min(timed_batch(tune, True) for _ in range(2))
+        out["two_sweep_batched_s"] = round(t2, 4)
+        out["two_sweep_GLUPs"] = round(lups / t2 / 1e9, 2)
+    if loop:
+        # per-problem loop: each problem solved on its own with the plain solver
+        run_s = 0.0
+        wall0 = time.perf_counter()
+        for s in specs:
+            sol = Solver(s.n, bc=s.bc, seed=s.seed, pid=s.pid)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(sol.stream)
+            sol.run(s.iters, mode="graph")
+            e1.record(sol.stream)
+            e1.synchronize()
+            run_s += e0.elapsed_time(e1) * 1e-3
+            sol.close()
+        wall = time.perf_counter() - wall0
+        out.update({"per_problem_loop_s": round(run_s, 4), "per_problem_loop_GLUPs": round(lups / run_s / 1e9, 2),
+                    "per_problem_loop_wall_s": round(wall, 2), "speedup_vs_loop": round(run_s / tb, 3)})
+    return out
+
+
+def bench_batch(args):
+    fixed = getattr(args, "tune", "")
+    out = batch_bench(tune=tuple(int(v) for v in fixed.split(",")) if fixed else None,
+                      retune=getattr(args, "retune", False), batch_only=getattr(args, "batch_only", False),
+                      two_sweep=getattr(args, "batch_two_sweep", False))
     print(json.dumps(out), flush=True)

@@ -112,7 +112,9 @@ def test_batch_every_autotune_candidate_is_identical(env):
     probs = [_problem(api, s) for s in specs]
     iters = [s.iters for s in specs]
     ref = None
-    for cand in autotune.candidates(probs)[::5]:
+    cands = autotune.candidates(probs)[::5] + autotune.refinements([0, len(j3d.variants()) - 1])[::3]
+    assert len({c[1] for c in cands}) > 2 and len({c[2] for c in cands}) == 2
+    for cand in cands:
         with api.Batch(probs, iters, tune=cand) as b:
             res = b.run()
             outs = [b.get_interior(i) for i in range(len(specs))]
