@@ -399,6 +399,36 @@ j3d_status j3d_pool_usage(const j3d_pool *pl, int32_t *slots_used, uint64_t *byt
 
 j3d_status j3d_pool_destroy(j3d_pool *pl);
 
+/* ---- allocation-free solve ---------------------------------------------- */
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): a one-shot solve of
+ * problem p in FUSED mode (the j3d_run path) that calls no hipMalloc, hipFree,
+ * hipHostMalloc, stream, event or graph creation.
+ *  fields        caller device memory, 256-byte aligned, of at least
+ *                j3d_field_bytes(p) bytes (ENOMEM otherwise): the two iterates
+ *                of every block and their halo storage.  Contents on entry are
+ *                ignored; they hold the final state on return.
+ *  interior_in   device array, dense nx*ny*nz (x fastest): the initial
+ *                interior; NULL: the seeded interior of p (seed, pid).
+ *  interior_out  device array, dense nx*ny*nz: the interior after `iters`
+ *                sweeps.  Neither array may overlap `fields` (EINVAL).
+ *  iters         sweeps (>= 0).
+ *  residual_out  host pointer or NULL: the last sweep's residual (0 for
+ *                iters == 0); with it the call synchronises at the end.
+ * The descriptor, tile and map tables live in a static device array of
+ * 4 MiB per GPU (held until the process ends): EINVAL for a problem whose
+ * tables need more (about 16 000 blocks).  The call uploads those tables
+ * from host memory and synchronises the stream once before its first launch.
+ * Every call on a GPU shares that GPU's array, so calls that overlap on one
+ * GPU (other threads or streams) race; run them one at a time per GPU.
+ * Results are bit-identical to j3d_create + j3d_set_interior (or the seeded
+ * init) + j3d_run + j3d_get_interior.  EINVAL for NULL p / fields /
+ * interior_out, misaligned fields or iters < 0; all before device work.     */
+j3d_status j3d_solve_noalloc(const j3d_problem *p, void *fields, uint64_t fields_bytes,
+                             const double *interior_in, double *interior_out, int64_t iters,
+                             double *residual_out, void *hip_stream);
+
 /* ---- measurement helpers ------------------------------------------------- */
 
 /* Enqueue a plain device copy of `bytes` (multiple of 16) from src to dst: the

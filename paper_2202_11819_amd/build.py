@@ -26,7 +26,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wextra",
           "-Wno-unused-parameter", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
-KERNEL_SOURCES = ["j3d_kernels.hip", "j3d_twostep.hip"]
+KERNEL_SOURCES = ["j3d_kernels.hip", "j3d_twostep.hip", "j3d_noalloc.hip"]
 HOST_SOURCES = ["j3d_plan.cpp", "j3d_solver.cpp", "j3d_pool.cpp"]
 
 

@@ -119,6 +119,7 @@ _SIGS = {
     "j3d_pool_poll": ([_H, POINTER(c_int32), c_int32, POINTER(c_int32), POINTER(c_int32)], c_int),
     "j3d_pool_result": ([_H, c_int32, _DP, POINTER(c_int64)], c_int),
     "j3d_pool_fetch": ([_H, c_int32, c_void_p, _DP, POINTER(c_int64)], c_int),
+    "j3d_solve_noalloc": ([_P, c_void_p, c_uint64, c_void_p, c_void_p, c_int64, _DP, c_void_p], c_int),
     "j3d_pool_release": ([_H, c_int32], c_int),
     "j3d_pool_usage": ([_H, POINTER(c_int32), POINTER(c_uint64)], c_int),
     "j3d_pool_destroy": ([_H], c_int),
@@ -416,6 +417,18 @@ def j3d_pool_fetch(h, slot: int, host_dst_ptr=None):
     _check(_lib.j3d_pool_fetch(h, int(slot), c_void_p(host_dst_ptr) if host_dst_ptr else None, byref(r),
                                byref(it)), "j3d_pool_fetch")
     return r.value, it.value
+
+
+def j3d_solve_noalloc(p: Problem, fields_ptr, fields_bytes, interior_in_ptr, interior_out_ptr, iters,
+                      residual=False, stream_ptr=None):
+    """One-shot fused solve with no device allocation (pointers are device
+    addresses; interior_in_ptr None: seeded).  Returns the residual or None."""
+    r = c_double(0.0)
+    _check(_lib.j3d_solve_noalloc(byref(p.c), c_void_p(fields_ptr), int(fields_bytes),
+                                  c_void_p(interior_in_ptr) if interior_in_ptr else None,
+                                  c_void_p(interior_out_ptr), int(iters), byref(r) if residual else None,
+                                  c_void_p(stream_ptr) if stream_ptr else None), "j3d_solve_noalloc")
+    return r.value if residual else None
 
 
 def j3d_pool_release(h, slot: int):
