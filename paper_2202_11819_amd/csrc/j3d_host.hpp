@@ -105,7 +105,7 @@ inline int64_t row_pitch(int64_t ex) { return ex; }
 // Cells of one block's field (one parity), halos included.
 inline int64_t block_field_cells(int64_t ex, int64_t ey, int64_t ez)
 {
-    return row_pitch(ex) * (ey + 2) * (ez + 2);
+    return plane_stride(row_pitch(ex), ey) * (ez + 2);
 }
 
 inline uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }

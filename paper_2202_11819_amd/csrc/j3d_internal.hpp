@@ -4,13 +4,15 @@
 // two iterates (parity 0 and 1; Sec. III-C keeps two copies of the block and
 // swaps their roles every iteration):
 //
-//   field  F[p][b]: (ez+2) planes x (ey+2) rows x pitch doubles, x fastest,
-//          pitch = ex (rows unpadded: a plane is one contiguous run).  Plane 0
+//   field  F[p][b]: (ez+2) planes of (ey+2) rows x pitch doubles, x fastest,
+//          pitch = ex (rows unpadded: the rows of a plane are one contiguous
+//          run); the plane stride plane_stride(ex, ey) rounds (ey+2)*ex up to
+//          16 cells so that every plane starts on a 128-byte line.  Plane 0
 //          and plane ez+1 hold the z- / z+ halos, row 0 and row ey+1 of every
 //          plane hold the y- / y+ halos; interior cell (x, y, z) sits at
-//          ((z+1)*(ey+2) + (y+1))*pitch + x.  Rows carry no x ghosts, so a row
-//          of the interior and a y- or z-halo row are the same contiguous ex
-//          doubles; edge rows of the halo planes are never read.
+//          (z+1)*plane_stride + (y+1)*pitch + x.  Rows carry no x ghosts, so a
+//          row of the interior and a y- or z-halo row are the same contiguous
+//          ex doubles; edge rows of the halo planes are never read.
 //   x-halo X[p][b]: two arrays of ey*ez doubles (x- then x+), y fastest.  The
 //          x-halos live apart from the rows so that a neighbour writes them as
 //          contiguous runs instead of one double per row.
@@ -32,6 +34,10 @@
 namespace j3d {
 
 // Face numbering: 0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+.  opp(f) = f ^ 1.
+
+// Plane stride of a block's field in doubles: (ey+2) rows of ex cells,
+// rounded up to a multiple of 16 cells (128 bytes).
+constexpr int64_t plane_stride(int64_t ex, int64_t ey) { return ((ey + 2) * ex + 15) / 16 * 16; }
 
 struct BlockDesc {          // 128 bytes, read by kernels through scalar loads
     int64_t off[2];         // F[p][b] offset, in doubles from the arena base
@@ -109,10 +115,12 @@ VariantInfo variant_info(int v);
 // (f % nxv, f / nxv)), so no lane idles except in the tile's last partial
 // wave.  Rows are stored unpadded (pitch = width), so a tile of whole rows is
 // one contiguous run of memory per plane: consecutive lanes read and write
-// consecutive doubles, and only the run's two end lines are shared with the
-// neighbouring tiles.  Per block the tile covers whole rows, hy of them with
-// ex * hy <= cap (cells per thread budget), as long as the halo ring still has
-// one loader thread per cell with that many rows (2 * (ex + hy) <= nt).
+// consecutive doubles.  Planes start on 128-byte lines; a tile of whole rows
+// whose first cell is not on a line shifts its slots by up to 15 (slots before
+// the first cell idle), so that every wave covers whole lines.  Per block the
+// tile covers whole rows, hy of them with ex * hy <= cap (cap - 15 for widths
+// off the 16-cell grid, room for the shift), as long as the halo ring still
+// has one loader thread per cell with that many rows (2 * (ex + hy) <= nt).
 // Wider blocks are cut into tnx pieces of at most flat_max_x(nt) columns (each
 // after the first starting on a 16-column boundary) and y into tny near-equal
 // pieces of at most hy rows, with wx * hy <= cap and 2 * (wx + hy) <= nt, wx
@@ -123,14 +131,16 @@ struct FlatShape {
 constexpr int flat_max_x(int nt) { return nt >= 512 ? 192 : nt / 2 - 32; }
 constexpr FlatShape flat_shape(int ex, int ey, int nt, int cap)
 {
-    int tnx = 1, wx = ex;
-    const int rows = cap / ex < ey ? cap / ex : ey;
+    const int capw = ex % 16 ? cap - 15 : cap;  // whole rows: room for the alignment shift
+    int tnx = 1, wx = ex, budget = capw;
+    const int rows = capw / ex < ey ? capw / ex : ey;
     if (rows < 1 || nt / 2 - ex < rows) {  // the ring would limit whole rows: cut x
         const int mx = flat_max_x(nt);
         tnx = (ex + mx - 1) / mx;
         wx = tnx == 1 ? ex : (ex + tnx - 1) / tnx + 15;
+        budget = tnx == 1 ? capw : cap;
     }
-    int hy = cap / wx;
+    int hy = budget / wx;
     if (nt / 2 - wx < hy) hy = nt / 2 - wx;
     if (ey < hy) hy = ey;
     if (hy < 1) hy = 1;

@@ -166,7 +166,7 @@ struct Tiled {
     __device__ static int lx(int) { return LXC; }
     __device__ static bool full(int nxv, int nyv) { return nxv == TX && nyv == TY; }
     template <bool FULL>
-    __device__ static bool cell(int tid, int r, int nxv, int nyv, int &cx, int &cy)
+    __device__ static bool cell(int tid, int r, int nxv, int nyv, int, int &cx, int &cy)
     {
         cx = tid % TX;
         cy = tid / TX + NTY * r;
@@ -212,14 +212,15 @@ struct Flat {
     static_assert(NT % 64 == 0 && NT >= 256, "whole waves, room for a halo ring");
     static_assert(PF >= 1 && PF <= 4, "prefetch depth");
     __device__ static int lx(int nxv) { return nxv + 2; }
-    // every slot of every thread holds a cell (no idle tail)
+    // every slot of every thread holds a cell (no idle tail, no shift)
     __device__ static bool full(int nxv, int nyv) { return nxv * nyv == CAP; }
+    // shift: slots before the tile's first cell (aligns waves to lines)
     template <bool FULL>
-    __device__ static bool cell(int tid, int r, int nxv, int nyv, int &cx, int &cy)
+    __device__ static bool cell(int tid, int r, int nxv, int nyv, int shift, int &cx, int &cy)
     {
-        const int f = tid + r * NT;
+        const int f = tid + r * NT - shift;
         const int q = f / nxv, x = f - q * nxv;
-        const bool v = FULL || q < nyv;
+        const bool v = FULL || (f >= 0 && q < nyv);
         cy = v ? q : 0;
         cx = v ? x : 0;
         return v;
@@ -255,6 +256,7 @@ struct TileGeo {
     uint64_t psb;      // plane stride of this block's field, bytes
     int ex, ey, ez, pitch;  // pitch: row stride in doubles (>= ex)
     int x0, y0, z0, nxv, nyv, nzv;
+    int shift;         // flattened tiles of whole rows: slots before the first cell
     bool want_res;
 };
 
@@ -293,7 +295,7 @@ __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *_
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         int cx, cy;
-        vr[r] = K::template cell<FULL>(tid, r, g.nxv, g.nyv, cx, cy);
+        vr[r] = K::template cell<FULL>(tid, r, g.nxv, g.nyv, g.shift, cx, cy);
         off[r] = vr[r] ? (uint32_t)(g.y0 + cy + 1) * rowb + (uint32_t)(g.x0 + cx) * 8u : kOutside;
         li[r] = vr[r] ? (cy + 1) * lx + cx + 1 : lx + 1;
         lw[r] = vr[r] ? li[r] : K::SINK + (tid & 63);
@@ -424,7 +426,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
     g.ez = B->ext[2];
     g.pitch = B->pitch;
     const int ex = g.ex, ey = g.ey, ez = g.ez, pitch = g.pitch;
-    g.psb = (uint64_t)(ey + 2) * pitch * 8u;
+    g.psb = (uint64_t)plane_stride(pitch, ey) * 8u;
     char *base = reinterpret_cast<char *>(a.base);
     g.cur = base + B->off[p] * 8;
     g.nxt = base + B->off[p ^ 1] * 8;
@@ -461,7 +463,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
     g.zhi = g.cur + (uint64_t)(ez + 1) * g.psb;
     g.dxm = g.dxp = g.nxt;
     g.xrm = g.xrp = 0;
-    const uint64_t ps = (uint64_t)(ey + 2) * pitch;  // plane stride, doubles
+    const uint64_t ps = (uint64_t)plane_stride(pitch, ey);  // plane stride, doubles
     const double *curd = a.base + B->off[p];
     const double *ym_src = curd + ps + (uint64_t)g.y0 * pitch;                 // row y0-1, plane 0
     const double *yp_src = curd + ps + (uint64_t)(g.y0 + g.nyv + 1) * pitch;  // row y0+nyv, plane 0
@@ -478,13 +480,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
         }
         if (g.y0 == 0 && B->nbr[2] >= 0) {
             const BlockDesc *N = a.blocks + B->nbr[2];
-            const uint64_t psn = (uint64_t)(N->ext[1] + 2) * pitch;
+            const uint64_t psn = (uint64_t)plane_stride(pitch, N->ext[1]);
             ym_src = a.base + N->off[p] + psn + (uint64_t)N->ext[1] * pitch;
             ym_step = psn;
         }
         if (g.y0 + g.nyv == ey && B->nbr[3] >= 0) {
             const BlockDesc *N = a.blocks + B->nbr[3];
-            const uint64_t psn = (uint64_t)(N->ext[1] + 2) * pitch;
+            const uint64_t psn = (uint64_t)plane_stride(pitch, N->ext[1]);
             yp_src = a.base + N->off[p] + psn + pitch;
             yp_step = psn;
         }
@@ -535,7 +537,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
         }
     }
 
-    const bool full = K::full(g.nxv, g.nyv);
+    // a tile of whole rows starts its slots on the line that holds its first
+    // cell (planes start on lines), so every wave reads and writes whole lines
+    g.shift = g.nxv == pitch ? (int)(((int64_t)(g.y0 + 1) * pitch) & 15) : 0;
+    const bool full = K::full(g.nxv, g.nyv) && g.shift == 0;
     const double rmax = full ? sweep_planes<K, true>(g, hsrc0, hstep, hl, sm, xf)
                              : sweep_planes<K, false>(g, hsrc0, hstep, hl, sm, xf);
 
@@ -614,7 +619,7 @@ __device__ __forceinline__ FaceGeom face_geom(const BlockDesc &B)
     g.ey = B.ext[1];
     g.ez = B.ext[2];
     g.pitch = B.pitch;
-    g.PS = (g.ey + 2) * g.pitch;
+    g.PS = (int)plane_stride(g.pitch, g.ey);
     g.fx = g.ey * g.ez;
     g.fy = g.ex * g.ez;
     g.fz = g.ex * g.ey;
@@ -732,7 +737,7 @@ __global__ __launch_bounds__(256) void shell_kernel(double *base, const BlockDes
         const int64_t plane = (int64_t)ex * ey;
         const int64_t full = (ez >= 2 ? 2 : 1) * plane;
         const int64_t ring = (ex <= 2 || ey <= 2) ? plane : 2 * (int64_t)ex + 2 * (int64_t)(ey - 2);
-        const int64_t ps = (int64_t)(ey + 2) * pitch;
+        const int64_t ps = plane_stride(pitch, ey);
         const double *cur = base + B.off[parity];
         double *nxt = base + B.off[parity ^ 1];
         const double *X = base + B.xoff[parity];
@@ -788,15 +793,21 @@ __global__ __launch_bounds__(256) void init_kernel(double *base, const BlockDesc
     for (int bb = blockIdx.y; bb < nblocks; bb += gridDim.y) {
         const BlockDesc &B = blocks[block_begin + bb];
         const int ey = B.ext[1], ez = B.ext[2], pitch = B.pitch;
-        const int64_t cells = (int64_t)pitch * (ey + 2) * (ez + 2);
+        const int64_t ps = plane_stride(pitch, ey), rows = (int64_t)(ey + 2) * pitch;
+        const int64_t cells = ps * (ez + 2);
         double *F0 = base + B.off[0];
         double *F1 = base + B.off[1];
         double *Fp = parity ? F1 : F0;
         const int64_t stride = (int64_t)gridDim.x * blockDim.x;
         for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < cells; idx += stride) {
-            const int x = (int)(idx % pitch);
-            const int64_t rr = idx / pitch;
-            const int yy = (int)(rr % (ey + 2)), zz = (int)(rr / (ey + 2));
+            const int zz = (int)(idx / ps);
+            const int64_t w = idx - (int64_t)zz * ps;
+            if (w >= rows) {  // padding at the end of a plane: never read as data
+                F0[idx] = 0.0;
+                F1[idx] = 0.0;
+                continue;
+            }
+            const int x = (int)(w % pitch), yy = (int)(w / pitch);
             const bool oy = (yy == 0 || yy == ey + 1), oz = (zz == 0 || zz == ez + 1);
             if (!oy && !oz) {
                 if (write_interior) {
@@ -844,7 +855,7 @@ __device__ __forceinline__ int64_t dense_to_block(const BlockDesc *blocks, int b
     const int bz = m.mz[2 * k], lz = m.mz[2 * k + 1];
     const BlockDesc &B = blocks[block_base + bx + m.nb0 * (by + m.nb1 * bz)];
     const int pitch = B.pitch, ey = B.ext[1];
-    return B.off[parity] + (int64_t)(lz + 1) * (ey + 2) * pitch + (int64_t)(ly + 1) * pitch + lx;
+    return B.off[parity] + (int64_t)(lz + 1) * plane_stride(pitch, ey) + (int64_t)(ly + 1) * pitch + lx;
 }
 
 __global__ __launch_bounds__(256) void scatter_kernel(double *base, const BlockDesc *blocks,
@@ -905,7 +916,7 @@ __global__ __launch_bounds__(256) void set_face_kernel(double *base, const Block
         }
         const BlockDesc &B = blocks[block_base + bx + m.nb0 * (by + m.nb1 * bz)];
         const int pitch = B.pitch, ey = B.ext[1], ez = B.ext[2];
-        const int64_t PS = (int64_t)(ey + 2) * pitch;
+        const int64_t PS = plane_stride(pitch, ey);
         const double v = src[g];
         for (int q = 0; q < 2; ++q) {
             if (axis == 0) {
@@ -926,7 +937,7 @@ __global__ __launch_bounds__(256) void gather_block_kernel(const double *base,
     const BlockDesc &B = blocks[block];
     const int ex = B.ext[0], ey = B.ext[1], ez = B.ext[2];
     const int64_t count = (int64_t)ex * ey * ez;
-    const int64_t PS = (int64_t)(ey + 2) * B.pitch;
+    const int64_t PS = plane_stride(B.pitch, ey);
     const double *F = base + B.off[parity];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < count; g += stride) {

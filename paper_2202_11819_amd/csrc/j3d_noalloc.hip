@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void xhalo_pull_kernel(double *base, const Blo
         for (int side = 0; side < 2; ++side) {
             if (B.nbr[side] < 0) continue;
             const BlockDesc &N = blocks[B.nbr[side]];
-            const int64_t nps = (int64_t)(N.ext[1] + 2) * N.pitch;
+            const int64_t nps = plane_stride(N.pitch, N.ext[1]);
             const double *F = base + N.off[parity] + (side == 0 ? N.ext[0] - 1 : 0);
             for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < fx;
                  i += (int64_t)gridDim.x * blockDim.x) {

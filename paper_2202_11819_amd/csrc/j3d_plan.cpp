@@ -144,7 +144,7 @@ j3d_status resolve_decomp(const j3d_problem *p, Decomp *d)
                     return set_error(J3D_EINVAL, "block %lldx%lldx%lld exceeds 2^31 cells with halos",
                                      (long long)ex, (long long)ey, (long long)ez);
                 // the sweep addresses one plane (with its ghost rows) by 32-bit byte offsets
-                if ((ey + 2) * row_pitch(ex) * 8 > INT32_MAX)
+                if (plane_stride(row_pitch(ex), ey) * 8 > INT32_MAX)
                     return set_error(J3D_EINVAL, "block %lldx%lldx%lld: an x-y plane exceeds 2^28 cells",
                                      (long long)ex, (long long)ey, (long long)ez);
             }

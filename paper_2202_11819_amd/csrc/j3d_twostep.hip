@@ -122,7 +122,7 @@ __global__ __launch_bounds__(S::NT) void twostep_kernel(TwoStepArgs a)
     const int x0 = tx * TX, nxv = min(TX, ex - x0);
     const int y0 = (int)((int64_t)ty * ey / nty), nyv = (int)((int64_t)(ty + 1) * ey / nty) - y0;
     const int z0 = (int)((int64_t)tz * ez / ntz), nzv = (int)((int64_t)(tz + 1) * ez / ntz) - z0;
-    const int64_t ps = (int64_t)(ey + 2) * pitch;  // plane stride of the field, doubles
+    const int64_t ps = plane_stride(pitch, ey);  // plane stride of the field, doubles
 
     // u^t sources.  Cell (gx, gy) of the tile's two-cell ring, plane z:
     //   inside the grid in x and y: the field, planes -1 .. ez (the ghost
