@@ -87,10 +87,12 @@ typedef enum {
  *                 every face copied to page-locked host memory (into the
  *                 receiver's slot), each block's received faces copied back,
  *                 then unpack and update.
- *  HOST_OVERLAP:  HOST_STAGED with the update running on a second stream while
- *                 the faces are in transit (Fig. 1's overlap of computation
- *                 and communication); the cells that read a halo are then
- *                 recomputed from the delivered halos.
+ *  HOST_OVERLAP:  HOST_STAGED with Fig. 1's split of the update: while the
+ *                 faces are in transit, a second stream updates each block's
+ *                 interior (the cells whose six neighbours lie inside the
+ *                 block); once they are delivered and unpacked, the exterior
+ *                 (the one-cell shell that reads halos) is updated.  Every
+ *                 cell is written once per iteration.
  *  TWO_SWEEP:     two iterations per launch (temporal blocking) on a grid of
  *                 one block: each workgroup computes the intermediate iterate
  *                 on its tile plus a one-cell ring in LDS and writes only

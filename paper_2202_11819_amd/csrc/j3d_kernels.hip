@@ -716,9 +716,10 @@ __global__ __launch_bounds__(256) void unpack_kernel(double *base, const BlockDe
 // ---- block shell update -------------------------------------------------------
 //
 // The cells of a block that read a halo (its outer one-cell shell) updated from
-// the current halo storage, with the same expression and order as the sweep.
-// Used after an update that ran while the halos were still in transit: the
-// interior cells were already right, the shell cells are recomputed.
+// the current halo storage, with the same expression and order as the sweep:
+// Fig. 1's exterior update, run once the halos have been unpacked, after the
+// interior update (a sweep clipped to the halo-free cells, SW_INNER) ran
+// while they were in transit.
 
 __device__ __forceinline__ int64_t shell_cells(int ex, int ey, int ez)
 {

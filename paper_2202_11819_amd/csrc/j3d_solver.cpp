@@ -501,9 +501,10 @@ j3d_status ensure_host_mirror(j3d_solver *s)
     return J3D_OK;
 }
 
-// One iteration with the exchange staged through host memory.  overlap: the
-// update runs on a side stream while the faces travel, and the shell cells
-// (the ones that read a halo) are recomputed once the halos are unpacked.
+// One iteration with the exchange staged through host memory.  overlap
+// (Fig. 1): the interior update (the cells that read no halo) runs on a side
+// stream while the faces travel, and the exterior update (the one-cell shell
+// of each block) runs once the halos are unpacked; every cell is written once.
 j3d_status run_host_staged(j3d_solver *s, int p, bool res, bool overlap, hipStream_t main)
 {
     const Plan &plan = s->plan;
