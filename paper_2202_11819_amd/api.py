@@ -174,7 +174,11 @@ class Pool:
         return slot
 
     def step(self, sweeps=50):
+        """Enqueue one round.  Returns whether a round is in flight afterwards:
+        False when no admitted request was still running (all finished ones
+        wait for their result copy or their release), so nothing was enqueued."""
         C.j3d_pool_step(self.h, sweeps)
+        return C.j3d_pool_poll(self.h, 0)[1]
 
     def set_policy(self, fill_cells, max_wait_rounds=32, backlog_share=0):
         C.j3d_pool_set_policy(self.h, fill_cells, max_wait_rounds, backlog_share)

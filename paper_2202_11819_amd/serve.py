@@ -86,9 +86,10 @@ def serve_pool(trace, budget_bytes, max_slots=256, round_sweeps=50, check_every=
                 waiting.popleft()
                 active[slot] = i
             if not busy and active:
-                pool.step(round_sweeps)
-                rounds += 1
-                busy = True
+                busy = pool.step(round_sweeps)
+                rounds += busy
+                if not busy:  # every admitted request has finished: their result copies are in flight
+                    time.sleep(0.0002)
             elif not active and not waiting and pending:
                 # idle until the next arrival
                 gap = trace[pending[0]].arrival - (time.perf_counter() - t0)
