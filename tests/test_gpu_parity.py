@@ -130,6 +130,25 @@ def test_every_tile_shape_and_schedule(env):
                 assert r == want_r
 
 
+def test_unpadded_rows_and_line_shifted_tiles(env):
+    # Rows are unpadded and planes start on 128-byte lines; a flattened tile of
+    # whole rows whose first cell is not on a line shifts its slots.  Widths off
+    # the 16-cell grid with many y-tiles per plane make every shift 0..15 occur;
+    # width 1 and tiny planes cover the edge of the plane padding.
+    oracle, api, j3d = env
+    flat = [v for v, (tx, ty, nt) in enumerate(j3d.variants()) if tx == 0]
+    bc = (0.75, -0.5, 0.25, 1.0, -1.0, 0.5)
+    for n in [(17, 301, 5), (33, 97, 9), (100, 64, 7), (250, 40, 6), (1, 77, 3), (15, 15, 15), (241, 3, 4)]:
+        want, want_r, _ = oracle.jacobi(n, 6, bc=bc, seed=13, nthreads=NTH)
+        for v in flat:
+            say(f"shape {n} variant {v}")
+            with api.Solver(n, bc=bc, seed=13) as s:
+                s.set_tune(v, 4, 0)
+                r = s.run(6, mode="fused", residual=True)
+                assert np.array_equal(s.get_interior(), want), (n, v)
+                assert r == want_r, (n, v)
+
+
 def test_linear_field_with_per_cell_faces_is_fixed(env):
     oracle, api, _ = env
     n = (40, 24, 18)

@@ -235,3 +235,16 @@ def test_pool_entry_points_validate_before_device_work():
     with pytest.raises(j3d.J3DError) as e:
         j3d.j3d_pool_request_bytes(j3d.Problem((64, 64, 64), (2, 1, 1)))
     assert e.value.status == j3d.J3D_EINVAL
+
+
+def test_flattened_tile_shapes_fit_their_variants(tmp_path):
+    # the shape rule shared by the planner and the kernel, checked exhaustively
+    # on the host (widths 1..1200, heights 1..700, every thread count / capacity)
+    import subprocess
+    exe = tmp_path / "flat_shape_check"
+    src = os.path.join(ROOT, "tests", "flat_shape_check.cpp")
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-I", os.path.join(ROOT, "paper_2202_11819_amd", "csrc"),
+                           "-I", os.path.join(ROOT, "include"), src, "-o", str(exe)])
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0, out.stdout[-2000:]
+    assert " 0 bad" in out.stdout
