@@ -7,6 +7,7 @@
 // sweep tiles.
 #pragma once
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -70,6 +71,40 @@ j3d_status make_plan(int32_t count, const j3d_problem *probs, bool with_sr, Plan
 // by block, z then y then x slowest to fastest.
 void make_tiles(const Plan &plan, int32_t b0, int32_t b1, int variant, int zchunk,
                 std::vector<Tile> *tiles, std::vector<int32_t> *block_first);
+
+// Prefix sums of the estimated time of each tile (the planes it reads, plus
+// one for its first memory latency): prefix[i] covers tiles [0, i).
+// zchunk_eff: the z-chunk the kernels read (> 0); blocks: the table the
+// tiles index.
+void tile_work(const BlockDesc *blocks, int variant, int zchunk_eff, const std::vector<Tile> &tiles,
+               std::vector<uint64_t> *prefix);
+
+// Cuts tiles [t0, t0+cnt) into one contiguous range per XCD of about equal
+// work (SweepArgs::xcut) and returns the grid that covers the longest range
+// (kXcdCount workgroups per range index).  Launches too small to matter keep
+// equal counts: xcut stays zero and the grid is cnt.
+inline int xcd_split(const std::vector<uint64_t> &prefix, int32_t t0, int32_t cnt, int32_t *xcut)
+{
+    for (int x = 0; x <= kXcdCount; ++x) xcut[x] = 0;
+    // below a few tiles per compute unit the launch is short and equal counts do
+    if (cnt < 4 * 256 || prefix.size() < (size_t)t0 + cnt + 1) return cnt;
+    const uint64_t w0 = prefix[t0], total = prefix[t0 + cnt] - w0;
+    int longest = 0;
+    for (int x = 1; x <= kXcdCount; ++x) {
+        int32_t c = cnt;
+        if (x < kXcdCount) {
+            // first tile boundary at or past the target, or the one before if nearer
+            const uint64_t target = w0 + (uint64_t)((__uint128_t)total * x / kXcdCount);
+            const auto it = std::lower_bound(prefix.begin() + t0, prefix.begin() + t0 + cnt + 1, target);
+            c = (int32_t)(it - (prefix.begin() + t0));
+            if (c > 0 && target - prefix[t0 + c - 1] < prefix[t0 + c] - target) --c;
+            c = std::max(c, xcut[x - 1]);
+        }
+        xcut[x] = c;
+        longest = std::max(longest, xcut[x] - xcut[x - 1]);
+    }
+    return kXcdCount * std::max(longest, 1);
+}
 
 // Default sweep shape for the blocks of a plan.
 void default_tune(const Plan &plan, int cus, j3d_tune *t);

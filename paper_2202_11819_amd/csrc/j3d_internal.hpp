@@ -26,6 +26,7 @@
 // sizes ey*ez, ey*ez, ex*ez, ex*ez, ex*ey, ex*ey (Fig. 1's send_halo/recv_halo).
 #pragma once
 
+#include <cstddef>
 #include <cstdint>
 #include <vector>
 
@@ -81,21 +82,30 @@ enum : int32_t {
                     // interior update): every tile clipped to [1, e-1) on each axis
 };
 
+constexpr int kXcdCount = 8;  // XCDs (each with its own L2) per MI355X
+
 struct SweepArgs {
-    double *base;                 // arena base
-    const BlockDesc *blocks;
-    const ProbDesc *probs;
+    // A workgroup first reads the fields of the first 64 bytes (one scalar
+    // cache line): where its tile is.
     const Tile *tiles;
-    unsigned long long *res;      // residual words (bit patterns of non-negative doubles)
-    unsigned int *queue;          // persistent mode: 2 x 8 tile counters
-    int64_t step;                 // multi mode: sweep index of this launch
     int32_t tile_begin;
+    // One workgroup per tile: XCD x runs tiles [xcut[x], xcut[x+1]) of the
+    // launch (relative to tile_begin); launch_sweep fills equal counts when
+    // the caller leaves them all zero.
+    int32_t xcut[kXcdCount + 1];
     int32_t tile_count;
     int32_t zchunk;
     int32_t parity;               // plain mode: parity of the input iterate
     int32_t flags;
+    double *base;                 // arena base
+    const BlockDesc *blocks;
+    const ProbDesc *probs;
+    unsigned long long *res;      // residual words (bit patterns of non-negative doubles)
+    unsigned int *queue;          // persistent mode: 2 x 8 tile counters
+    int64_t step;                 // multi mode: sweep index of this launch
     int32_t queue_slot;           // persistent mode: which half of `queue` this launch uses
 };
+static_assert(offsetof(SweepArgs, flags) + sizeof(int32_t) <= 64, "tile lookup fields in one 64-byte line");
 
 // ---- kernel variants ----------------------------------------------------------
 

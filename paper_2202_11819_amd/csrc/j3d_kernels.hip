@@ -30,7 +30,7 @@ namespace {
 
 constexpr double kW = 1.0 / 7.0;                    // fl(1/7)
 constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;  // SplitMix64 Weyl increment
-constexpr int kXcds = 8;                            // XCDs per MI355X
+constexpr int kXcds = kXcdCount;
 
 __device__ __forceinline__ uint64_t splitmix64_mix(uint64_t z)
 {
@@ -73,16 +73,6 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Workgroups of a launch are dispatched round-robin over the XCDs (workgroup
-// i to XCD i % 8).  Give each XCD a contiguous run of tiles so that tiles
-// sharing halo rows run together under one L2.
-__device__ __forceinline__ int xcd_remap(int i, int n)
-{
-    const int q = n / kXcds, r = n % kXcds;
-    const int x = i % kXcds, j = i / kXcds;
-    return x * q + min(x, r) + j;
-}
-
 // ---- the sweep ----------------------------------------------------------------
 //
 // Addressing: every global access is a uniform (scalar) 64-bit base pointer
@@ -113,6 +103,12 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, uint64_t b
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0,
                                              (int)(bytes > 0x7fffffffull ? 0x7fffffffull : bytes),
                                              kRsrcWord3);
+}
+
+// A resource of at most 2 GiB - 1 (a plane or a face row): no clamp needed.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc32(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, kRsrcWord3);
 }
 
 template <int AUX>
@@ -260,7 +256,7 @@ struct TileGeo {
     bool want_res;
 };
 
-template <class K, bool FULL>
+template <class K, bool FULL, bool RES>
 __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *__restrict__ hsrc0,
                                                uint64_t hstep, int hl, double *sm, double *xf)
 {
@@ -314,16 +310,10 @@ __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *_
         if (g.x0 + g.nxv == g.ex) xop = (uint32_t)(g.y0 + tid - g.nyv) * 8u;
     }
     const uint64_t psb = g.psb;
+    const uint32_t psz = (uint32_t)psb;  // a plane is far below 2 GiB (checked by the planner)
     const int zend = g.z0 + g.nzv;  // last plane read: the z+ neighbour of the last one computed
     auto plane = [&](int z) -> const char * {
         return z < 0 ? g.zlo : (z >= g.ez ? g.zhi : g.cur + (uint64_t)(z + 1) * psb);
-    };
-    // x faces of plane k, taken from xf buffer `buf`
-    auto store_xfaces = [&](int k, int buf, bool any) __attribute__((always_inline)) {
-        const double xv = xf[buf * 2 * K::XROWS + xs];
-        const uint64_t fo = any ? (uint64_t)k * g.ey * 8u : 0u;
-        bstore<0>(rsrc(g.dxm + fo, any ? g.xrm : 0u), xom, xv);
-        bstore<0>(rsrc(g.dxp + fo, any ? g.xrp : 0u), xop, xv);
     };
 
     double R[NB][RY];
@@ -333,7 +323,7 @@ __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *_
     for (int j = 0; j < NB; ++j) {
         const int z = g.z0 - 1 + j;
         const bool live = z <= zend;
-        const __amdgpu_buffer_rsrc_t rz = rsrc(plane(live ? z : zend), live ? psb : 0);
+        const __amdgpu_buffer_rsrc_t rz = rsrc32(plane(live ? z : zend), live ? psz : 0u);
 #pragma unroll
         for (int r = 0; r < RY; ++r) R[j][r] = bload<kAuxLoad>(rz, off[r]);
         const int zh = z < g.z0 ? g.z0 : (z < zend ? z : zend - 1);
@@ -341,17 +331,30 @@ __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *_
     }
     double rmax = 0.0;
 
+    // Addresses that move by one plane per step, kept as running values (the
+    // step is short of scalar issue slots when every wave recomputes them).
+    char *op = g.nxt + (uint64_t)(g.z0 + 1) * psb;        // output plane z0+kk
+    int zn = g.z0 - 1 + NB;                                // plane refilled by step kk
+    const char *lp = g.cur + (uint64_t)(zn + 1) * psb;    // ... its address inside the field
+    const double *hp = hsrc0 + (uint64_t)(zn < zend ? zn : zend - 1) * hstep;  // its halo value
+    const uint64_t xstep = (uint64_t)g.ey * 8u;
+    uint64_t xo = (uint64_t)(int64_t)(g.z0 - 1) * xstep;  // x-face plane z0+kk-1 (unused at kk = 0)
+
     auto step = [&](const int kk, const int j) __attribute__((always_inline)) {
-        const int k = g.z0 + kk;
         const int jm = j, jc = (j + 1) % NB, jp = (j + 2) % NB;
         double *L = sm + (kk & 1) * K::PLANE;
 #pragma unroll
         for (int r = 0; r < RY; ++r) L[lw[r]] = R[jc][r];
         if (hl >= 0) L[hl] = H[jc];
         lds_barrier();
-        store_xfaces(k - 1, (kk + 1) & 1, kk > 0);
+        {   // x faces of plane k-1 (none before the first step)
+            const bool any = kk > 0;
+            const double xv = xf[((kk + 1) & 1) * 2 * K::XROWS + xs];
+            bstore<0>(rsrc32(g.dxm + xo, any ? g.xrm : 0u), xom, xv);
+            bstore<0>(rsrc32(g.dxp + xo, any ? g.xrp : 0u), xop, xv);
+        }
 
-        const __amdgpu_buffer_rsrc_t ro = rsrc(g.nxt + (uint64_t)(k + 1) * psb, psb);
+        const __amdgpu_buffer_rsrc_t ro = rsrc32(op, psz);
         double *XF = xf + (kk & 1) * 2 * K::XROWS;
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
@@ -367,21 +370,26 @@ __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *_
             bstore<kAuxStore>(ro, off[r], v);
             if (fxm[r]) XF[ly[r]] = v;
             if (fxp[r]) XF[K::XROWS + ly[r]] = v;
-            if (g.want_res) {
+            if (RES) {
                 const double d = vr[r] ? fabs(v - R[jc][r]) : 0.0;
                 rmax = d > rmax ? d : rmax;
             }
         }
         // refill the slot of plane k-1 with plane k-1+NB; past the tile's
         // last plane the resource is empty (loads return 0)
-        const int zn = k - 1 + NB;
-        const bool live = zn <= zend;
-        const __amdgpu_buffer_rsrc_t rn = rsrc(plane(live ? zn : zend), live ? psb : 0);
+        {
+            const bool live = zn <= zend;
+            const __amdgpu_buffer_rsrc_t rn = rsrc32(zn < g.ez ? lp : g.zhi, live ? psz : 0u);
 #pragma unroll
-        for (int r = 0; r < RY; ++r) R[jm][r] = bload<kAuxLoad>(rn, off[r]);
-        H[jm] = hsrc0[(uint64_t)(zn < zend ? zn : zend - 1) * hstep];
+            for (int r = 0; r < RY; ++r) R[jm][r] = bload<kAuxLoad>(rn, off[r]);
+            H[jm] = *hp;
+        }
+        op += psb;
+        lp += psb;
+        ++zn;
+        hp += zn < zend ? hstep : 0;
+        xo += xstep;
     };
-
     int kk = 0;
     if (g.nzv >= NB) {
         // one peeled round, then the steady state
@@ -396,7 +404,12 @@ __device__ __forceinline__ double sweep_planes(const TileGeo &g, const double *_
     for (int j = 0; j < NB - 1; ++j)
         if (kk + j < g.nzv) step(kk + j, j);
     lds_barrier();
-    store_xfaces(zend - 1, (g.nzv - 1) & 1, true);
+    {   // x faces of the last plane
+        const double xv = xf[((g.nzv - 1) & 1) * 2 * K::XROWS + xs];
+        const uint64_t fo = (uint64_t)(zend - 1) * xstep;
+        bstore<0>(rsrc32(g.dxm + fo, g.xrm), xom, xv);
+        bstore<0>(rsrc32(g.dxp + fo, g.xrp), xop, xv);
+    }
     return rmax;
 }
 
@@ -541,8 +554,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
     // cell (planes start on lines), so every wave reads and writes whole lines
     g.shift = g.nxv == pitch ? (int)(((int64_t)(g.y0 + 1) * pitch) & 15) : 0;
     const bool full = K::full(g.nxv, g.nyv) && g.shift == 0;
-    const double rmax = full ? sweep_planes<K, true>(g, hsrc0, hstep, hl, sm, xf)
-                             : sweep_planes<K, false>(g, hsrc0, hstep, hl, sm, xf);
+    // the residual's compare-and-select code only in the sweeps that want it
+    const double rmax = full ? (g.want_res ? sweep_planes<K, true, true>(g, hsrc0, hstep, hl, sm, xf)
+                                           : sweep_planes<K, true, false>(g, hsrc0, hstep, hl, sm, xf))
+                             : (g.want_res ? sweep_planes<K, false, true>(g, hsrc0, hstep, hl, sm, xf)
+                                           : sweep_planes<K, false, false>(g, hsrc0, hstep, hl, sm, xf));
 
     if (g.want_res) {
         // max over the workgroup, then one atomic per tile; the maximum of
@@ -570,8 +586,26 @@ __global__ __launch_bounds__(K::NT) void sweep_kernel(SweepArgs a)
     __shared__ double sm[K::SMEM];
     __shared__ double red[K::NT / 64];
     __shared__ double xf[4 * K::XROWS];
-    const int t = xcd_remap(blockIdx.x, gridDim.x);
-    sweep_tile<K>(a, a.tiles[a.tile_begin + t], sm, red, xf);
+    // Workgroups are dispatched round-robin over the XCDs (workgroup i to XCD
+    // i mod 8).  XCD x runs the contiguous run of tiles xcut[x] ..
+    // xcut[x+1]-1 in order, so tiles sharing halo rows run together under one
+    // L2.
+    // (xcut[x], xcut[x+1]) come straight from the launch arguments by index:
+    // one load, issued with the others, instead of a chain of selects that
+    // every wave would run.
+    const int x = blockIdx.x % kXcds, j = blockIdx.x / kXcds;
+    typedef const __attribute__((address_space(4))) int32_t kint32;
+    typedef const __attribute__((address_space(4))) char kchar;
+    const kint32 *xc = (const kint32 *)((kchar *)__builtin_amdgcn_kernarg_segment_ptr() + offsetof(SweepArgs, xcut));
+    const int lo = xc[x], hi = xc[x + 1];
+    // A workgroup past its XCD's run (runs differ in length) exits.  The test
+    // reads the tile's descriptor and the block table's address (never null),
+    // so that every launch argument the tile needs is fetched ahead of it
+    // rather than after it.
+    const int t = lo + j;
+    const Tile tl = a.tiles[a.tile_begin + min(t, a.tile_count - 1)];
+    if ((t >= hi ? -1 : tl.block) < 0 || a.blocks == nullptr) return;  // uniform
+    sweep_tile<K>(a, tl, sm, red, xf);
 }
 
 // Persistent form: a grid of a few workgroups per compute unit; per-XCD
@@ -1069,8 +1103,19 @@ int launch_sweep(int variant, const SweepArgs &a, int grid, void *stream)
 {
     if (variant < 0 || variant >= kVariantCount || grid < 1) return (int)hipErrorInvalidValue;
     const VariantEntry &e = kVariants[variant];
-    hipLaunchKernelGGL((a.flags & SW_PERSIST) ? e.persistent : e.fn, dim3(grid), dim3(e.threads), 0,
-                       (hipStream_t)stream, a);
+    if (a.flags & SW_PERSIST) {
+        hipLaunchKernelGGL(e.persistent, dim3(grid), dim3(e.threads), 0, (hipStream_t)stream, a);
+        return (int)hipGetLastError();
+    }
+    SweepArgs b = a;
+    if (b.xcut[kXcds] == 0) {
+        // equal counts: XCD x takes q or q+1 tiles, which a grid of one
+        // workgroup per tile covers exactly
+        if (grid != b.tile_count) return (int)hipErrorInvalidValue;
+        const int q = b.tile_count / kXcds, r = b.tile_count % kXcds;
+        for (int x = 0; x <= kXcds; ++x) b.xcut[x] = x * q + (x < r ? x : r);
+    }
+    hipLaunchKernelGGL(e.fn, dim3(grid), dim3(e.threads), 0, (hipStream_t)stream, b);
     return (int)hipGetLastError();
 }
 

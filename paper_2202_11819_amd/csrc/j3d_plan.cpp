@@ -319,6 +319,28 @@ void make_tiles(const Plan &plan, int32_t b0, int32_t b1, int variant, int zchun
     if (block_first) block_first->push_back((int32_t)tiles->size());
 }
 
+void tile_work(const BlockDesc *blocks, int variant, int zchunk_eff, const std::vector<Tile> &tiles,
+               std::vector<uint64_t> *prefix)
+{
+    // A tile's time is set by the planes it streams, whatever share of its
+    // lanes hold a cell (measured: weighting by cells balanced the batched
+    // workload worse than equal counts), plus a fixed cost of about one plane
+    // for its first memory latency.
+    (void)variant;
+    constexpr uint64_t kTileFixed = 1;  // planes
+    const int zc = zchunk_eff > 0 ? zchunk_eff : 1;
+    prefix->assign(tiles.size() + 1, 0);
+    uint64_t acc = 0;
+    for (size_t i = 0; i < tiles.size(); ++i) {
+        const Tile &t = tiles[i];
+        const int64_t ez = blocks[t.block].ext[2];
+        const int64_t ntz = ceil_div(ez, zc);
+        const int64_t nzv = (int64_t)(t.tz + 1) * ez / ntz - (int64_t)t.tz * ez / ntz;
+        acc += (uint64_t)(nzv + 2) + kTileFixed;
+        (*prefix)[i + 1] = acc;
+    }
+}
+
 void default_tune(const Plan &plan, int cus, j3d_tune *t)
 {
     // Shapes measured fastest on MI355X (one workgroup per tile; the

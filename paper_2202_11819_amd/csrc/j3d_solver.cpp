@@ -188,6 +188,7 @@ struct j3d_solver {
     int zchunk = 1;
     int32_t ntiles = 0;
     std::vector<Tile> tiles;
+    std::vector<uint64_t> work;  // prefix sums of the tiles' estimated work
     std::vector<int32_t> block_first;
     uint32_t persist_launches = 0;
     hipStream_t cap_stream = nullptr;
@@ -232,6 +233,7 @@ j3d_status apply_tune(j3d_solver *s, const j3d_tune &t)
     if (st != J3D_OK) return st;
     s->tune = t;
     s->zchunk = zc;
+    tile_work(s->plan.blocks.data(), t.variant, zc, tiles, &s->work);
     s->tiles.swap(tiles);
     s->block_first.swap(first);
     s->ntiles = (int32_t)s->tiles.size();
@@ -263,11 +265,13 @@ j3d_status sweep(j3d_solver *s, int parity, bool fused, bool res, int32_t t0, in
     a.tile_count = cnt;
     a.parity = parity;
     a.flags = (fused ? SW_FUSED : 0) | (res ? SW_RES : 0);
-    int grid = cnt;
+    int grid;
     if (s->tune.blocks_per_cu > 0) {
         a.flags |= SW_PERSIST;
         a.queue_slot = slot;
         grid = std::min(cnt, s->cus * s->tune.blocks_per_cu);
+    } else {
+        grid = xcd_split(s->work, t0, cnt, a.xcut);
     }
     return hip_status(launch_sweep(s->tune.variant, a, grid, st), "sweep launch");
 }
@@ -903,6 +907,7 @@ struct j3d_batch {
     int zchunk = 1;
     std::vector<int32_t> order;         // problems by iteration count, descending
     std::vector<int32_t> prefix_tiles;  // tiles of the first k problems of `order`
+    std::vector<uint64_t> work;         // prefix sums of the tiles' estimated work
     int64_t max_iters = 0;
     bool ran = false;
     uint32_t persist_launches = 0;
@@ -966,6 +971,7 @@ j3d_status j3d_batch_create(int32_t count, const j3d_problem *probs, const int64
         b->prefix_tiles.push_back((int32_t)tiles.size());
     }
     b->max_iters = count > 0 ? iters[b->order[0]] : 0;
+    tile_work(b->plan.blocks.data(), t.variant, zc, tiles, &b->work);
     st = upload_tables(b->plan, b->arena, b->stream);
     if (st == J3D_OK) st = upload_tiles(b->plan, tiles, b->arena, b->stream);
     if (st == J3D_OK)
@@ -1007,11 +1013,13 @@ j3d_status j3d_batch_run(j3d_batch *b, double *residuals_out)
         a.tile_begin = 0;
         a.tile_count = b->prefix_tiles[active];
         a.flags = SW_FUSED | SW_MULTI;
-        int grid = a.tile_count;
+        int grid;
         if (b->tune.blocks_per_cu > 0) {
             a.flags |= SW_PERSIST;
             a.queue_slot = (int)(b->persist_launches++ & 1);
-            grid = std::min(grid, b->cus * b->tune.blocks_per_cu);
+            grid = std::min(a.tile_count, b->cus * b->tune.blocks_per_cu);
+        } else {
+            grid = xcd_split(b->work, 0, a.tile_count, a.xcut);
         }
         st = hip_status(launch_sweep(b->tune.variant, a, grid, b->stream), "batch sweep launch");
         if (st != J3D_OK) return st;
@@ -1095,11 +1103,13 @@ j3d_status j3d_batch_run_two_sweep(j3d_batch *b, double *residuals_out)
         a.step = 0;
         a.tile_count = b->prefix_tiles[count];
         a.flags = SW_FUSED | SW_MULTI;
-        int grid = a.tile_count;
+        int grid;
         if (b->tune.blocks_per_cu > 0) {
             a.flags |= SW_PERSIST;
             a.queue_slot = (int)(b->persist_launches++ & 1);
-            grid = std::min(grid, b->cus * b->tune.blocks_per_cu);
+            grid = std::min(a.tile_count, b->cus * b->tune.blocks_per_cu);
+        } else {
+            grid = xcd_split(b->work, 0, a.tile_count, a.xcut);
         }
         st = hip_status(launch_sweep(b->tune.variant, a, grid, b->stream), "batch sweep launch");
         if (st != J3D_OK) return st;

@@ -248,3 +248,16 @@ def test_flattened_tile_shapes_fit_their_variants(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True)
     assert out.returncode == 0, out.stdout[-2000:]
     assert " 0 bad" in out.stdout
+
+
+def test_xcd_ranges_partition_each_launch(tmp_path):
+    # the per-XCD tile ranges of a one-workgroup-per-tile launch: in order,
+    # equal work within one tile, every tile run exactly once by the grid
+    import subprocess
+    exe = tmp_path / "xcd_split_check"
+    src = os.path.join(ROOT, "tests", "xcd_split_check.cpp")
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-I", os.path.join(ROOT, "paper_2202_11819_amd", "csrc"),
+                           "-I", os.path.join(ROOT, "include"), src, "-o", str(exe)])
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0, out.stdout[-2000:]
+    assert " 0 bad" in out.stdout
