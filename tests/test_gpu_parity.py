@@ -130,6 +130,18 @@ def test_every_tile_shape_and_schedule(env):
                 assert r == want_r
 
 
+def test_xcd_runs_of_unequal_length(env):
+    # 1216 tiles of 7 or 8 planes (32 per plane, 512-cell flattened tiles):
+    # each XCD's run of tiles is cut by streamed planes, so the runs differ
+    # in length (150 to 162 tiles) and the surplus workgroups of the shorter
+    # ones exit; every tile must still run exactly once
+    oracle, api, _ = env
+    bc = (0.5, -0.25, 1.0, 0.125, -1.0, 0.75)
+    for mode in ("fused", "graph", "unfused_phase"):
+        check(oracle, api, (64, 256, 300), nblk=(1, 1, 2), split=(None, None, [44, 256]), bc=bc, iters=6,
+              mode=mode, seed=11, tune=(33, 8, 0))
+
+
 def test_unpadded_rows_and_line_shifted_tiles(env):
     # Rows are unpadded and planes start on 128-byte lines; a flattened tile of
     # whole rows whose first cell is not on a line shifts its slots.  Widths off
