@@ -16,7 +16,7 @@ plain solves with p50/p99 latency (--headline-only skips them).
 
 Other workloads (--workload): modes, sweep (1024^3 decompositions), batch,
 serve, odf, hostex, twostep; each prints its own JSON lines.  Multi-GPU runs
-are not part of this build: --gpus above 1 exits with a message.
+are not part of the library: --gpus above 1 exits with a message.
 """
 from __future__ import annotations
 
@@ -528,7 +528,7 @@ def main():
     ap.add_argument("--odf-sweeps", type=int, default=20, help="odf workload: timed sweeps per mode")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(every block of the decomposition sits on one MI355X).", file=sys.stderr)
         sys.exit(2)
     import torch
