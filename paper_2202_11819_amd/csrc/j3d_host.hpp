@@ -76,7 +76,7 @@ void make_tiles(const Plan &plan, int32_t b0, int32_t b1, int variant, int zchun
 // one for its first memory latency): prefix[i] covers tiles [0, i).
 // zchunk_eff: the z-chunk the kernels read (> 0); blocks: the table the
 // tiles index.
-void tile_work(const BlockDesc *blocks, int variant, int zchunk_eff, const std::vector<Tile> &tiles,
+void tile_work(const BlockDesc *blocks, int zchunk_eff, const std::vector<Tile> &tiles,
                std::vector<uint64_t> *prefix);
 
 // Cuts tiles [t0, t0+cnt) into one contiguous range per XCD of about equal

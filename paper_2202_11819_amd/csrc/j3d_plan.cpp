@@ -319,14 +319,13 @@ void make_tiles(const Plan &plan, int32_t b0, int32_t b1, int variant, int zchun
     if (block_first) block_first->push_back((int32_t)tiles->size());
 }
 
-void tile_work(const BlockDesc *blocks, int variant, int zchunk_eff, const std::vector<Tile> &tiles,
+void tile_work(const BlockDesc *blocks, int zchunk_eff, const std::vector<Tile> &tiles,
                std::vector<uint64_t> *prefix)
 {
     // A tile's time is set by the planes it streams, whatever share of its
     // lanes hold a cell (measured: weighting by cells balanced the batched
     // workload worse than equal counts), plus a fixed cost of about one plane
     // for its first memory latency.
-    (void)variant;
     constexpr uint64_t kTileFixed = 1;  // planes
     const int zc = zchunk_eff > 0 ? zchunk_eff : 1;
     prefix->assign(tiles.size() + 1, 0);
