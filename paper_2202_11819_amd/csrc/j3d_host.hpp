@@ -68,16 +68,13 @@ struct Plan {
 j3d_status make_plan(int32_t count, const j3d_problem *probs, bool with_sr, Plan *plan);
 
 // Tiles of blocks [b0, b1) for a variant and z-chunk (0 = whole block), block
-// by block, z then y then x slowest to fastest.
+// by block, z then y then x slowest to fastest, each with the cells it covers.
 void make_tiles(const Plan &plan, int32_t b0, int32_t b1, int variant, int zchunk,
                 std::vector<Tile> *tiles, std::vector<int32_t> *block_first);
 
 // Prefix sums of the estimated time of each tile (the planes it reads, plus
 // one for its first memory latency): prefix[i] covers tiles [0, i).
-// zchunk_eff: the z-chunk the kernels read (> 0); blocks: the table the
-// tiles index.
-void tile_work(const BlockDesc *blocks, int zchunk_eff, const std::vector<Tile> &tiles,
-               std::vector<uint64_t> *prefix);
+void tile_work(const std::vector<Tile> &tiles, std::vector<uint64_t> *prefix);
 
 // Cuts tiles [t0, t0+cnt) into one contiguous range per XCD of about equal
 // work (SweepArgs::xcut) and returns the grid that covers the longest range

@@ -68,10 +68,18 @@ static_assert(sizeof(ProbDesc) == 64, "ProbDesc layout");
 
 enum : int32_t { PF_RES_LAST = 1 };
 
-// One sweep tile: block index and tile coordinates along x, y, z.
+// One sweep tile: block index, tile coordinates along x, y, z, and the cells
+// it covers (x0.., y0.., z0.., extents nxv, nyv, nzv), worked out on the host
+// when the table is built, so a workgroup reads its rectangle instead of
+// recomputing it (every wave would run the divisions on the compute unit's
+// one scalar unit).
 struct Tile {
     int32_t block, tx, ty, tz;
+    int32_t x0, y0, z0;
+    int32_t nxv, nyv, nzv;
+    int32_t pad[2];
 };
+static_assert(sizeof(Tile) == 48, "Tile layout");
 
 enum : int32_t {
     SW_FUSED = 1,   // halos from the neighbours (y, z read directly; x faces handed over)

@@ -181,14 +181,6 @@ struct Tiled {
         c = u % TY;
         return u < 2 * TY && c < nyv;
     }
-    __device__ static void rect(const Tile tl, int ex, int ey, int &x0, int &nxv, int &y0, int &nyv)
-    {
-        const int nty = (ey + TY - 1) / TY;
-        x0 = tl.tx * TX;
-        nxv = min(TX, ex - x0);
-        y0 = (int)((int64_t)tl.ty * ey / nty);
-        nyv = (int)((int64_t)(tl.ty + 1) * ey / nty) - y0;
-    }
 };
 
 // Flattened tiles: the rectangle's cells, numbered x fastest, are dealt to
@@ -230,14 +222,6 @@ struct Flat {
         if (kind == 2 && h >= nyv) { h -= nyv; kind = 3; }
         c = h;
         return kind < 3 || h < nyv;
-    }
-    __device__ static void rect(const Tile tl, int ex, int ey, int &x0, int &nxv, int &y0, int &nyv)
-    {
-        const FlatShape s = flat_shape(ex, ey, NT, CAP);
-        x0 = flat_x0(ex, s.tnx, tl.tx);
-        nxv = flat_x0(ex, s.tnx, tl.tx + 1) - x0;
-        y0 = (int)((int64_t)tl.ty * ey / s.tny);
-        nyv = (int)((int64_t)(tl.ty + 1) * ey / s.tny) - y0;
     }
 };
 
@@ -443,14 +427,14 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
     char *base = reinterpret_cast<char *>(a.base);
     g.cur = base + B->off[p] * 8;
     g.nxt = base + B->off[p ^ 1] * 8;
-    // z is cut into n = ceil(ez / zchunk) near-equal pieces, so no tile is a
-    // thin remainder along it.
-    K::rect(tl, ex, ey, g.x0, g.nxv, g.y0, g.nyv);
-    {
-        const int ntz = (ez + a.zchunk - 1) / a.zchunk;
-        g.z0 = (int)((int64_t)tl.tz * ez / ntz);
-        g.nzv = (int)((int64_t)(tl.tz + 1) * ez / ntz) - g.z0;
-    }
+    // the tile's cells, as the host cut them (flat_shape / fixed columns,
+    // near-equal pieces along y and z)
+    g.x0 = tl.x0;
+    g.nxv = tl.nxv;
+    g.y0 = tl.y0;
+    g.nyv = tl.nyv;
+    g.z0 = tl.z0;
+    g.nzv = tl.nzv;
     if (a.flags & SW_INNER) {
         // Fig. 1's interior update: the cells that read no halo, i.e. the tile
         // clipped to [1, e-1) along every axis (uniform over the workgroup)

@@ -311,31 +311,46 @@ void make_tiles(const Plan &plan, int32_t b0, int32_t b1, int variant, int zchun
         if (block_first) block_first->push_back((int32_t)tiles->size());
         int64_t ntx, nty;
         tiles_xy(vi, B.ext[0], B.ext[1], &ntx, &nty);
-        const int ntz = (int)ceil_div(B.ext[2], zc);
+        const int ex = B.ext[0], ey = B.ext[1], ez = B.ext[2];
+        const int ntz = (int)ceil_div(ez, zc);
+        // z is cut into ntz near-equal pieces, so no tile is a thin remainder
         for (int tz = 0; tz < ntz; ++tz)
             for (int ty = 0; ty < (int)nty; ++ty)
-                for (int tx = 0; tx < (int)ntx; ++tx) tiles->push_back(Tile{b, tx, ty, tz});
+                for (int tx = 0; tx < (int)ntx; ++tx) {
+                    Tile t{};
+                    t.block = b;
+                    t.tx = tx;
+                    t.ty = ty;
+                    t.tz = tz;
+                    if (vi.tile_x == 0) {  // flattened: x pieces on 16-column boundaries, y near-equal
+                        const FlatShape f = flat_shape(ex, ey, vi.threads, vi.tile_y);
+                        t.x0 = flat_x0(ex, f.tnx, tx);
+                        t.nxv = flat_x0(ex, f.tnx, tx + 1) - t.x0;
+                    } else {  // fixed: TX-wide columns, y near-equal
+                        t.x0 = tx * vi.tile_x;
+                        t.nxv = std::min(vi.tile_x, ex - t.x0);
+                    }
+                    t.y0 = (int32_t)((int64_t)ty * ey / nty);
+                    t.nyv = (int32_t)((int64_t)(ty + 1) * ey / nty) - t.y0;
+                    t.z0 = (int32_t)((int64_t)tz * ez / ntz);
+                    t.nzv = (int32_t)((int64_t)(tz + 1) * ez / ntz) - t.z0;
+                    tiles->push_back(t);
+                }
     }
     if (block_first) block_first->push_back((int32_t)tiles->size());
 }
 
-void tile_work(const BlockDesc *blocks, int zchunk_eff, const std::vector<Tile> &tiles,
-               std::vector<uint64_t> *prefix)
+void tile_work(const std::vector<Tile> &tiles, std::vector<uint64_t> *prefix)
 {
     // A tile's time is set by the planes it streams, whatever share of its
     // lanes hold a cell (measured: weighting by cells balanced the batched
     // workload worse than equal counts), plus a fixed cost of about one plane
     // for its first memory latency.
     constexpr uint64_t kTileFixed = 1;  // planes
-    const int zc = zchunk_eff > 0 ? zchunk_eff : 1;
     prefix->assign(tiles.size() + 1, 0);
     uint64_t acc = 0;
     for (size_t i = 0; i < tiles.size(); ++i) {
-        const Tile &t = tiles[i];
-        const int64_t ez = blocks[t.block].ext[2];
-        const int64_t ntz = ceil_div(ez, zc);
-        const int64_t nzv = (int64_t)(t.tz + 1) * ez / ntz - (int64_t)t.tz * ez / ntz;
-        acc += (uint64_t)(nzv + 2) + kTileFixed;
+        acc += (uint64_t)(tiles[i].nzv + 2) + kTileFixed;
         (*prefix)[i + 1] = acc;
     }
 }

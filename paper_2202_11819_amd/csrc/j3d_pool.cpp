@@ -481,7 +481,7 @@ j3d_status j3d_pool_step(j3d_pool *pl, int32_t sweeps)
     a.tile_begin = 0;
     a.tile_count = (int32_t)tiles.size();
     std::vector<uint64_t> work;
-    tile_work(pl->host_blocks, pl->zchunk, tiles, &work);
+    tile_work(tiles, &work);
     const int grid = xcd_split(work, 0, a.tile_count, a.xcut);
     const int32_t one_sweep_launches = pl->two_sweep ? (any_odd ? 1 : 0) : sweeps;
     for (int32_t j = 0; j < one_sweep_launches && st == J3D_OK; ++j) {

@@ -233,7 +233,7 @@ j3d_status apply_tune(j3d_solver *s, const j3d_tune &t)
     if (st != J3D_OK) return st;
     s->tune = t;
     s->zchunk = zc;
-    tile_work(s->plan.blocks.data(), zc, tiles, &s->work);
+    tile_work(tiles, &s->work);
     s->tiles.swap(tiles);
     s->block_first.swap(first);
     s->ntiles = (int32_t)s->tiles.size();
@@ -971,7 +971,7 @@ j3d_status j3d_batch_create(int32_t count, const j3d_problem *probs, const int64
         b->prefix_tiles.push_back((int32_t)tiles.size());
     }
     b->max_iters = count > 0 ? iters[b->order[0]] : 0;
-    tile_work(b->plan.blocks.data(), zc, tiles, &b->work);
+    tile_work(tiles, &b->work);
     st = upload_tables(b->plan, b->arena, b->stream);
     if (st == J3D_OK) st = upload_tiles(b->plan, tiles, b->arena, b->stream);
     if (st == J3D_OK)

@@ -316,7 +316,14 @@ void twostep_make_tiles(const BlockDesc *blocks, int32_t b0, int32_t b1, int zch
         twostep_tiles(blocks[b].ext[0], blocks[b].ext[1], blocks[b].ext[2], zchunk, &ntx, &nty, &ntz);
         for (int tz = 0; tz < ntz; ++tz)
             for (int ty = 0; ty < nty; ++ty)
-                for (int tx = 0; tx < ntx; ++tx) tiles->push_back(Tile{b, tx, ty, tz});
+                for (int tx = 0; tx < ntx; ++tx) {
+                    Tile t{};  // the two-sweep kernel cuts its own rectangle from tx, ty, tz
+                    t.block = b;
+                    t.tx = tx;
+                    t.ty = ty;
+                    t.tz = tz;
+                    tiles->push_back(t);
+                }
     }
 }
 
