@@ -420,7 +420,8 @@ j3d_status j3d_pool_destroy(j3d_pool *pl);
  *                iters == 0); with it the call synchronises at the end.
  * The descriptor, tile and map tables live in a static device array of
  * 4 MiB per GPU (held until the process ends): EINVAL for a problem whose
- * tables need more (about 16 000 blocks).  The call uploads those tables
+ * tables need more (256 bytes per block and 48 per tile: about 13 000 blocks
+ * of one tile each, fewer with more tiles).  The call uploads those tables
  * from host memory and synchronises the stream once before its first launch.
  * Every call on a GPU shares that GPU's array, so calls that overlap on one
  * GPU (other threads or streams) race; run them one at a time per GPU.

@@ -67,6 +67,42 @@ struct Plan {
 // (and at least the largest plane and face of every problem).
 j3d_status make_plan(int32_t count, const j3d_problem *probs, bool with_sr, Plan *plan);
 
+// Fills each block's fused-sweep halo sources and x-face targets (fx_*, fy_*,
+// fz_*) from its neighbour links and the neighbours' offsets; -1 where a face
+// has no neighbour.  Every block table the sweep reads must pass through it
+// once its offsets are final (the planner's and the pool's).
+inline void link_halo_sources(BlockDesc *blocks, size_t count)
+{
+    for (size_t b = 0; b < count; ++b) {
+        BlockDesc &B = blocks[b];
+        const int64_t ey = B.ext[1], ez = B.ext[2], pitch = B.pitch;
+        const int64_t ps = plane_stride(pitch, ey);
+        B.fy_step[0] = B.fy_step[1] = 0;
+        for (int q = 0; q < 2; ++q) {
+            B.fx_m[q] = B.fx_p[q] = B.fy_m[q] = B.fy_p[q] = B.fz_m[q] = B.fz_p[q] = -1;
+            if (B.nbr[0] >= 0) B.fx_m[q] = blocks[B.nbr[0]].xoff[q] + ey * ez;
+            if (B.nbr[1] >= 0) B.fx_p[q] = blocks[B.nbr[1]].xoff[q];
+            if (B.nbr[2] >= 0) {
+                const BlockDesc &N = blocks[B.nbr[2]];
+                const int64_t psn = plane_stride(pitch, N.ext[1]);
+                B.fy_m[q] = N.off[q] + psn + (int64_t)N.ext[1] * pitch;
+                B.fy_step[0] = psn;
+            }
+            if (B.nbr[3] >= 0) {
+                const BlockDesc &N = blocks[B.nbr[3]];
+                const int64_t psn = plane_stride(pitch, N.ext[1]);
+                B.fy_p[q] = N.off[q] + psn + pitch;
+                B.fy_step[1] = psn;
+            }
+            if (B.nbr[4] >= 0) {
+                const BlockDesc &N = blocks[B.nbr[4]];
+                B.fz_m[q] = N.off[q] + (int64_t)N.ext[2] * ps;
+            }
+            if (B.nbr[5] >= 0) B.fz_p[q] = blocks[B.nbr[5]].off[q] + ps;
+        }
+    }
+}
+
 // Tiles of blocks [b0, b1) for a variant and z-chunk (0 = whole block), block
 // by block, z then y then x slowest to fastest, each with the cells it covers.
 void make_tiles(const Plan &plan, int32_t b0, int32_t b1, int variant, int zchunk,

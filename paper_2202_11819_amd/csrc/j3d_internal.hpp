@@ -40,7 +40,7 @@ namespace j3d {
 // rounded up to a multiple of 16 cells (128 bytes).
 constexpr int64_t plane_stride(int64_t ex, int64_t ey) { return ((ey + 2) * ex + 15) / 16 * 16; }
 
-struct BlockDesc {          // 128 bytes, read by kernels through scalar loads
+struct BlockDesc {          // 256 bytes, read by kernels through scalar loads
     int64_t off[2];         // F[p][b] offset, in doubles from the arena base
     int64_t xoff[2];        // X[p][b] offset (x- array, then x+ array)
     int64_t sr_off;         // S[b] offset; R[b] follows at sr_off + face_total
@@ -51,8 +51,21 @@ struct BlockDesc {          // 128 bytes, read by kernels through scalar loads
     int32_t org[3];         // global coordinates of the block's first cell
     int32_t pitch;          // row stride of the field in doubles (= ex: rows unpadded)
     int32_t pad[6];
+    // Fused sweep: where this block's halos come from and where its x faces
+    // go, worked out from the neighbours when the plan is made (doubles from
+    // the arena base, per iterate parity; -1: no neighbour on that face, the
+    // own ghost layer serves), so a workgroup finds them in its own block's
+    // descriptor instead of through a chain of loads of the neighbours' ones.
+    int64_t fx_m[2];        // x- neighbour's X[q] x+ half: takes this block's x- face of iterate q
+    int64_t fx_p[2];        // x+ neighbour's X[q] x- half
+    int64_t fy_m[2];        // y- neighbour's F[p]: its last interior row, at plane index 0
+    int64_t fy_p[2];        // y+ neighbour's F[p]: its first interior row, at plane index 0
+    int64_t fz_m[2];        // z- neighbour's F[p]: its last interior plane
+    int64_t fz_p[2];        // z+ neighbour's F[p]: its first interior plane
+    int64_t fy_step[2];     // plane strides of the y- and y+ neighbours' fields, doubles
+    int64_t pad2[2];
 };
-static_assert(sizeof(BlockDesc) == 128, "BlockDesc layout");
+static_assert(sizeof(BlockDesc) == 256, "BlockDesc layout");
 
 // Problem state seen by the multi-problem sweep (batched and served forms).
 struct ProbDesc {           // 64 bytes

@@ -465,33 +465,28 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
     const double *ym_src = curd + ps + (uint64_t)g.y0 * pitch;                 // row y0-1, plane 0
     const double *yp_src = curd + ps + (uint64_t)(g.y0 + g.nyv + 1) * pitch;  // row y0+nyv, plane 0
     uint64_t ym_step = ps, yp_step = ps;
-    if (fused) {
+    if (fused) {  // the neighbours' places, precomputed in the block's descriptor
         const int q = p ^ 1;
-        if (B->nbr[0] >= 0) {
-            g.dxm = base + (a.blocks[B->nbr[0]].xoff[q] + (int64_t)ey * ez) * 8;
+        const int64_t xm = B->fx_m[q], xp = B->fx_p[q], ym = B->fy_m[p], yp = B->fy_p[p];
+        const int64_t zm = B->fz_m[p], zp = B->fz_p[p];
+        if (xm >= 0) {
+            g.dxm = base + xm * 8;
             g.xrm = (uint32_t)ey * 8u;
         }
-        if (B->nbr[1] >= 0) {
-            g.dxp = base + a.blocks[B->nbr[1]].xoff[q] * 8;
+        if (xp >= 0) {
+            g.dxp = base + xp * 8;
             g.xrp = (uint32_t)ey * 8u;
         }
-        if (g.y0 == 0 && B->nbr[2] >= 0) {
-            const BlockDesc *N = a.blocks + B->nbr[2];
-            const uint64_t psn = (uint64_t)plane_stride(pitch, N->ext[1]);
-            ym_src = a.base + N->off[p] + psn + (uint64_t)N->ext[1] * pitch;
-            ym_step = psn;
+        if (g.y0 == 0 && ym >= 0) {
+            ym_src = a.base + ym;
+            ym_step = (uint64_t)B->fy_step[0];
         }
-        if (g.y0 + g.nyv == ey && B->nbr[3] >= 0) {
-            const BlockDesc *N = a.blocks + B->nbr[3];
-            const uint64_t psn = (uint64_t)plane_stride(pitch, N->ext[1]);
-            yp_src = a.base + N->off[p] + psn + pitch;
-            yp_step = psn;
+        if (g.y0 + g.nyv == ey && yp >= 0) {
+            yp_src = a.base + yp;
+            yp_step = (uint64_t)B->fy_step[1];
         }
-        if (B->nbr[4] >= 0) {
-            const BlockDesc *N = a.blocks + B->nbr[4];
-            g.zlo = base + N->off[p] * 8 + (uint64_t)N->ext[2] * g.psb;
-        }
-        if (B->nbr[5] >= 0) g.zhi = base + a.blocks[B->nbr[5]].off[p] * 8 + g.psb;
+        if (zm >= 0) g.zlo = base + zm * 8;
+        if (zp >= 0) g.zhi = base + zp * 8;
     }
 
     // Halo loader role: at most one ring cell of the LDS plane per thread.

@@ -287,6 +287,7 @@ j3d_status make_plan(int32_t count, const j3d_problem *probs, bool with_sr, Plan
     if (with_sr)
         for (BlockDesc &B : plan->blocks)
             B.sr_off = (int64_t)(bump.take(2 * (uint64_t)B.face_total * sizeof(double)) / sizeof(double));
+    link_halo_sources(plan->blocks.data(), plan->blocks.size());
     uint64_t bounce = 0;
     for (const ProbPlan &pp : plan->probs) {
         const int64_t n0 = pp.d.n[0], n1 = pp.d.n[1], n2 = pp.d.n[2];

@@ -339,6 +339,7 @@ j3d_status j3d_pool_admit(j3d_pool *pl, const j3d_problem *p, int64_t max_iters,
     r.blk.pitch = (int32_t)row_pitch(d.n[0]);
     r.blk.prob = s;
     r.blk.face_total = 2 * (d.n[1] * d.n[2] + d.n[0] * d.n[2] + d.n[0] * d.n[1]);
+    link_halo_sources(&r.blk, 1);  // one block, no neighbours: every face reads the own ghost layer
     r.iters_done = 0;
     r.buf = 0;
     r.max_iters = max_iters;

@@ -261,3 +261,17 @@ def test_xcd_ranges_partition_each_launch(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True)
     assert out.returncode == 0, out.stdout[-2000:]
     assert " 0 bad" in out.stdout
+
+
+def test_fused_halo_sources_link_neighbours(tmp_path):
+    # the per-block halo sources the fused sweep reads: each equals the
+    # neighbour formula it replaces, -1 without a neighbour, and a lone block
+    # built from a zeroed descriptor (the pool's requests) reads its own ghosts
+    import subprocess
+    exe = tmp_path / "halo_link_check"
+    src = os.path.join(ROOT, "tests", "halo_link_check.cpp")
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-I", os.path.join(ROOT, "paper_2202_11819_amd", "csrc"),
+                           "-I", os.path.join(ROOT, "include"), src, "-o", str(exe)])
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0, out.stdout[-2000:]
+    assert " 0 bad" in out.stdout
