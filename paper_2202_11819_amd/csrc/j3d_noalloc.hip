@@ -133,6 +133,7 @@ extern "C" j3d_status j3d_solve_noalloc(const j3d_problem *p, void *fields, uint
             B.xoff[q] = (int64_t)o;
             o += 2ull * B.ext[1] * B.ext[2];
         }
+    link_halo_sources(plan.blocks.data(), plan.blocks.size());  // from the offsets just set
     if (fields_bytes < o * sizeof(double))
         return set_error(J3D_ENOMEM, "fields hold %llu bytes, %llu needed (j3d_field_bytes)",
                          (unsigned long long)fields_bytes, (unsigned long long)(o * sizeof(double)));
