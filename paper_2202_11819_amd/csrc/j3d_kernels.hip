@@ -401,8 +401,14 @@ template <class K>
 __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, double *sm, double *red,
                                            double *xf)
 {
-    const BlockDesc *__restrict__ B = a.blocks + tl.block;
-    const ProbDesc *__restrict__ P = a.probs + B->prob;
+    // The descriptor tables are read-only while kernels run: reading them
+    // through the constant address space keeps every field a scalar load,
+    // whatever the compiler can prove about the pointers (a vector load would
+    // queue behind the planes' streams).
+    typedef const __attribute__((address_space(4))) BlockDesc KBlockDesc;
+    typedef const __attribute__((address_space(4))) ProbDesc KProbDesc;
+    KBlockDesc *B = (KBlockDesc *)(a.blocks + tl.block);
+    KProbDesc *P = (KProbDesc *)(a.probs + B->prob);
 
     TileGeo g;
     int p;
@@ -489,6 +495,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
         if (zp >= 0) g.zhi = base + zp * 8;
     }
 
+    const int64_t xh = B->xoff[p];  // own x-halo arrays of iterate p (before any per-lane branch)
     // Halo loader role: at most one ring cell of the LDS plane per thread.
     // hsrc0 points at plane index 0's value; plane k adds k*hstep doubles.
     const int tid = threadIdx.x;
@@ -507,7 +514,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
                 const int y = g.y0 + c;
                 if (kind == 2) {
                     if (g.x0 == 0) {
-                        hsrc0 = a.base + B->xoff[p] + y;
+                        hsrc0 = a.base + xh + y;
                         hstep = ey;
                     } else {
                         hsrc0 = curd + ps + (uint64_t)(y + 1) * pitch + g.x0 - 1;
@@ -517,7 +524,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
                 } else {
                     const int xr = g.x0 + g.nxv;
                     if (xr == ex) {
-                        hsrc0 = a.base + B->xoff[p] + (int64_t)ey * ez + y;
+                        hsrc0 = a.base + xh + (int64_t)ey * ez + y;
                         hstep = ey;
                     } else {
                         hsrc0 = curd + ps + (uint64_t)(y + 1) * pitch + xr;
