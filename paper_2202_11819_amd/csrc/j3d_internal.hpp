@@ -70,9 +70,8 @@ static_assert(sizeof(BlockDesc) == 256, "BlockDesc layout");
 // Problem state seen by the multi-problem sweep (batched and served forms).
 struct ProbDesc {           // 64 bytes
     int64_t base;           // sweeps already done when step 0 of this launch sequence runs
-    int64_t limit;          // sweep count at which the problem stops (the served form ends a round at
-                            // the request's next residual check)
-    int32_t pad1;
+    int64_t limit;          // sweep count at which the problem stops
+    int32_t check_every;    // residual every k-th sweep (0: only at `limit`)
     int32_t res_slot;       // index of the problem's residual word
     int32_t flags;          // PF_RES_LAST: evaluate the residual at `limit`
     int32_t pad0;
@@ -86,14 +85,12 @@ enum : int32_t { PF_RES_LAST = 1 };
 // it covers (x0.., y0.., z0.., extents nxv, nyv, nzv), worked out on the host
 // when the table is built, so a workgroup reads its rectangle instead of
 // recomputing it (every wave would run the divisions on the compute unit's
-// one scalar unit).  prob repeats the block's problem index, so that the
-// problem descriptor can be read together with the block's.
+// one scalar unit).
 struct Tile {
     int32_t block, tx, ty, tz;
     int32_t x0, y0, z0;
     int32_t nxv, nyv, nzv;
-    int32_t prob;
-    int32_t pad;
+    int32_t pad[2];
 };
 static_assert(sizeof(Tile) == 48, "Tile layout");
 

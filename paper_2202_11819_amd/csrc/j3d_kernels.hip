@@ -408,48 +408,31 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
     typedef const __attribute__((address_space(4))) BlockDesc KBlockDesc;
     typedef const __attribute__((address_space(4))) ProbDesc KProbDesc;
     KBlockDesc *B = (KBlockDesc *)(a.blocks + tl.block);
-    KProbDesc *P = (KProbDesc *)(a.probs + tl.prob);
-
-    // Every descriptor field the tile needs is read here, ahead of the first
-    // branch and for both iterate parities (a multi-problem sweep learns its
-    // parity from the problem descriptor, which comes in the same batch), and
-    // everything below picks among them with selects: the scalar loads go out
-    // together and the workgroup waits for them once.  Read where they are
-    // used, behind the branches that decide them, they formed a chain of
-    // about ten dependent waits per tile.
-    const int64_t pbase = P->base, plimit = P->limit;
-    const int32_t pflags = P->flags, res_slot = P->res_slot;
-    const int ex = B->ext[0], ey = B->ext[1], ez = B->ext[2], pitch = B->pitch;
-    const int64_t off0 = B->off[0], off1 = B->off[1], xoff0 = B->xoff[0], xoff1 = B->xoff[1];
-    const int64_t fxm0 = B->fx_m[0], fxm1 = B->fx_m[1], fxp0 = B->fx_p[0], fxp1 = B->fx_p[1];
-    const int64_t fym0 = B->fy_m[0], fym1 = B->fy_m[1], fyp0 = B->fy_p[0], fyp1 = B->fy_p[1];
-    const int64_t fzm0 = B->fz_m[0], fzm1 = B->fz_m[1], fzp0 = B->fz_p[0], fzp1 = B->fz_p[1];
-    const int64_t fys0 = B->fy_step[0], fys1 = B->fy_step[1];
-    // An empty statement that uses all of them: their loads are issued
-    // before it and waited for here, once.  Without it the compiler moves
-    // each load past the branches below, to its first use, and the workgroup
-    // waits on memory once per branch.
-    asm volatile("" ::"s"(pbase), "s"(plimit), "s"(pflags), "s"(res_slot), "s"(ex), "s"(ey), "s"(ez), "s"(pitch),
-                 "s"(off0), "s"(off1), "s"(xoff0), "s"(xoff1), "s"(fxm0), "s"(fxm1), "s"(fxp0), "s"(fxp1), "s"(fym0),
-                 "s"(fym1), "s"(fyp0), "s"(fyp1), "s"(fzm0), "s"(fzm1), "s"(fzp0), "s"(fzp1), "s"(fys0), "s"(fys1));
+    KProbDesc *P = (KProbDesc *)(a.probs + B->prob);
 
     TileGeo g;
-    const bool multi = (a.flags & SW_MULTI) != 0;
-    const int64_t t = pbase + a.step;
-    if (multi && t >= plimit) return;  // uniform over the workgroup
-    const int p = multi ? (int)(t & 1) : a.parity;
-    g.want_res = multi ? ((pflags & PF_RES_LAST) != 0 && t + 1 == plimit) : (a.flags & SW_RES) != 0;
+    int p;
+    if (a.flags & SW_MULTI) {
+        const int64_t t = P->base + a.step;
+        if (t >= P->limit) return;  // uniform over the workgroup
+        p = (int)(t & 1);
+        const int64_t t1 = t + 1;
+        g.want_res = ((P->flags & PF_RES_LAST) && t1 == P->limit) ||
+                     (P->check_every > 0 && t1 % P->check_every == 0);
+    } else {
+        p = a.parity;
+        g.want_res = (a.flags & SW_RES) != 0;
+    }
     const bool fused = (a.flags & SW_FUSED) != 0;
-    const int64_t offc = p ? off1 : off0, offn = p ? off0 : off1;
-    const int64_t xh = p ? xoff1 : xoff0;  // own x-halo arrays of iterate p
-    g.ex = ex;
-    g.ey = ey;
-    g.ez = ez;
-    g.pitch = pitch;
+    g.ex = B->ext[0];
+    g.ey = B->ext[1];
+    g.ez = B->ext[2];
+    g.pitch = B->pitch;
+    const int ex = g.ex, ey = g.ey, ez = g.ez, pitch = g.pitch;
     g.psb = (uint64_t)plane_stride(pitch, ey) * 8u;
     char *base = reinterpret_cast<char *>(a.base);
-    g.cur = base + offc * 8;
-    g.nxt = base + offn * 8;
+    g.cur = base + B->off[p] * 8;
+    g.nxt = base + B->off[p ^ 1] * 8;
     // the tile's cells, as the host cut them (flat_shape / fixed columns,
     // near-equal pieces along y and z)
     g.x0 = tl.x0;
@@ -478,25 +461,41 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
     // boundary, nothing is copied), and hands its x faces, which would be
     // strided reads for the neighbour, to the neighbours' x-halo arrays of the
     // next iterate.  Global-boundary faces always come from the own ghost
-    // layer, which holds the Dirichlet values.  The neighbours' places were
-    // worked out on the host (-1: no neighbour on that face); x faces go to
-    // the arrays of iterate p^1, y and z halos come from iterate p.
-    const int64_t xm = fused ? (p ? fxm0 : fxm1) : -1, xp = fused ? (p ? fxp0 : fxp1) : -1;
-    const int64_t ym = fused ? (p ? fym1 : fym0) : -1, yp = fused ? (p ? fyp1 : fyp0) : -1;
-    const int64_t zm = fused ? (p ? fzm1 : fzm0) : -1, zp = fused ? (p ? fzp1 : fzp0) : -1;
+    // layer, which holds the Dirichlet values.
+    g.zlo = g.cur;
+    g.zhi = g.cur + (uint64_t)(ez + 1) * g.psb;
+    g.dxm = g.dxp = g.nxt;
+    g.xrm = g.xrp = 0;
     const uint64_t ps = (uint64_t)plane_stride(pitch, ey);  // plane stride, doubles
-    const double *curd = a.base + offc;
-    const bool ynm = g.y0 == 0 && ym >= 0, ynp = g.y0 + g.nyv == ey && yp >= 0;
-    const double *ym_src = ynm ? a.base + ym : curd + ps + (uint64_t)g.y0 * pitch;             // row y0-1, plane 0
-    const double *yp_src = ynp ? a.base + yp : curd + ps + (uint64_t)(g.y0 + g.nyv + 1) * pitch;  // row y0+nyv
-    const uint64_t ym_step = ynm ? (uint64_t)fys0 : ps, yp_step = ynp ? (uint64_t)fys1 : ps;
-    g.zlo = zm >= 0 ? base + zm * 8 : g.cur;
-    g.zhi = zp >= 0 ? base + zp * 8 : g.cur + (uint64_t)(ez + 1) * g.psb;
-    g.dxm = xm >= 0 ? base + xm * 8 : g.nxt;
-    g.dxp = xp >= 0 ? base + xp * 8 : g.nxt;
-    g.xrm = xm >= 0 ? (uint32_t)ey * 8u : 0u;
-    g.xrp = xp >= 0 ? (uint32_t)ey * 8u : 0u;
+    const double *curd = a.base + B->off[p];
+    const double *ym_src = curd + ps + (uint64_t)g.y0 * pitch;                 // row y0-1, plane 0
+    const double *yp_src = curd + ps + (uint64_t)(g.y0 + g.nyv + 1) * pitch;  // row y0+nyv, plane 0
+    uint64_t ym_step = ps, yp_step = ps;
+    if (fused) {  // the neighbours' places, precomputed in the block's descriptor
+        const int q = p ^ 1;
+        const int64_t xm = B->fx_m[q], xp = B->fx_p[q], ym = B->fy_m[p], yp = B->fy_p[p];
+        const int64_t zm = B->fz_m[p], zp = B->fz_p[p];
+        if (xm >= 0) {
+            g.dxm = base + xm * 8;
+            g.xrm = (uint32_t)ey * 8u;
+        }
+        if (xp >= 0) {
+            g.dxp = base + xp * 8;
+            g.xrp = (uint32_t)ey * 8u;
+        }
+        if (g.y0 == 0 && ym >= 0) {
+            ym_src = a.base + ym;
+            ym_step = (uint64_t)B->fy_step[0];
+        }
+        if (g.y0 + g.nyv == ey && yp >= 0) {
+            yp_src = a.base + yp;
+            yp_step = (uint64_t)B->fy_step[1];
+        }
+        if (zm >= 0) g.zlo = base + zm * 8;
+        if (zp >= 0) g.zhi = base + zp * 8;
+    }
 
+    const int64_t xh = B->xoff[p];  // own x-halo arrays of iterate p (before any per-lane branch)
     // Halo loader role: at most one ring cell of the LDS plane per thread.
     // hsrc0 points at plane index 0's value; plane k adds k*hstep doubles.
     const int tid = threadIdx.x;
@@ -562,7 +561,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, const Tile tl, do
         if (tid == 0) {
             double w = 0.0;
             for (int i = 0; i < K::NT / 64; ++i) w = red[i] > w ? red[i] : w;
-            atomic_max_agent(a.res + res_slot, (unsigned long long)__double_as_longlong(w));
+            atomic_max_agent(a.res + P->res_slot, (unsigned long long)__double_as_longlong(w));
         }
     }
 }
@@ -591,11 +590,6 @@ __global__ __launch_bounds__(K::NT) void sweep_kernel(SweepArgs a)
     // rather than after it.
     const int t = lo + j;
     const Tile tl = a.tiles[a.tile_begin + min(t, a.tile_count - 1)];
-    // The whole descriptor and the launch arguments the tile needs in one
-    // wait: an empty statement that uses them keeps the compiler from moving
-    // their loads past the test below, where each would cost another wait.
-    asm volatile("" ::"s"(tl.block), "s"(tl.prob), "s"(tl.x0), "s"(tl.y0), "s"(tl.z0), "s"(tl.nxv), "s"(tl.nyv),
-                 "s"(tl.nzv), "s"(a.flags), "s"(a.parity), "s"(a.step), "s"(a.base), "s"(a.blocks), "s"(a.probs));
     if ((t >= hi ? -1 : tl.block) < 0 || a.blocks == nullptr) return;  // uniform
     sweep_tile<K>(a, tl, sm, red, xf);
 }

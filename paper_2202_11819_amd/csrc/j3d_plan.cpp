@@ -320,7 +320,6 @@ void make_tiles(const Plan &plan, int32_t b0, int32_t b1, int variant, int zchun
                 for (int tx = 0; tx < (int)ntx; ++tx) {
                     Tile t{};
                     t.block = b;
-                    t.prob = B.prob;
                     t.tx = tx;
                     t.ty = ty;
                     t.tz = tz;

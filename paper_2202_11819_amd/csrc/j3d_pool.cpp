@@ -464,10 +464,7 @@ j3d_status j3d_pool_step(j3d_pool *pl, int32_t sweeps)
         one.blocks.assign(1, r.blk);
         std::vector<Tile> t;
         make_tiles(one, 0, 1, pl->variant, pl->zchunk, &t, nullptr);
-        for (Tile &x : t) {
-            x.block = s;
-            x.prob = s;
-        }
+        for (Tile &x : t) x.block = s;
         tiles.insert(tiles.end(), t.begin(), t.end());
     }
     if (pl->round.empty()) return J3D_OK;

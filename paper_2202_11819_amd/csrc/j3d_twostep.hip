@@ -319,7 +319,6 @@ void twostep_make_tiles(const BlockDesc *blocks, int32_t b0, int32_t b1, int zch
                 for (int tx = 0; tx < ntx; ++tx) {
                     Tile t{};  // the two-sweep kernel cuts its own rectangle from tx, ty, tz
                     t.block = b;
-                    t.prob = blocks[b].prob;
                     t.tx = tx;
                     t.ty = ty;
                     t.tz = tz;
