@@ -275,3 +275,19 @@ def test_fused_halo_sources_link_neighbours(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True)
     assert out.returncode == 0, out.stdout[-2000:]
     assert " 0 bad" in out.stdout
+
+
+def test_tile_tables_cover_every_cell_once(tmp_path):
+    # the planner's sweep tiles, from the built library: inside the block,
+    # within the variant's shape and z-chunk, every cell exactly once, for
+    # every variant on ragged and aligned block shapes
+    import subprocess
+    pkg = os.path.join(ROOT, "paper_2202_11819_amd")
+    exe = tmp_path / "tile_cover_check"
+    src = os.path.join(ROOT, "tests", "tile_cover_check.cpp")
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+                           "-I", os.path.join(pkg, "csrc"), "-I", os.path.join(ROOT, "include"), src,
+                           "-o", str(exe), "-L", pkg, "-lj3d", f"-Wl,-rpath,{pkg}"])
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0, out.stdout[-2000:]
+    assert " 0 bad" in out.stdout
